@@ -1,0 +1,492 @@
+"""Pins of the CPU oracle against things other than itself: closed forms,
+library routines, invariants of the continuous problem, exact reproduction and
+convergence rates, and the DOF counts the paper prints.  CPU only."""
+import json
+import math
+import os
+
+import numpy as np
+import numpy.polynomial.legendre as npleg
+import pytest
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import basis, mesh, multigrid, operator, quadrature, solvers, adjoint, ionic
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _ev(s):
+    return float(eval(s, {"sqrt": math.sqrt}))
+
+
+# --- 1D rules -------------------------------------------------------------------
+
+def test_quadrature_closed_forms():
+    g = json.load(open(os.path.join(GOLD, "quadrature_closed_forms.json")))
+    for p, d in g["gll"].items():
+        x, w = quadrature.gll(int(p))
+        np.testing.assert_allclose(x, [_ev(s) for s in d["x"]], atol=1e-15)
+        np.testing.assert_allclose(w, [_ev(s) for s in d["w"]], rtol=1e-14)
+    for q, d in g["gauss"].items():
+        x, w = quadrature.gauss(int(q))
+        np.testing.assert_allclose(x, [_ev(s) for s in d["x"]], atol=1e-15)
+        np.testing.assert_allclose(w, [_ev(s) for s in d["w"]], rtol=1e-14)
+
+
+@pytest.mark.parametrize("q", range(1, 14))
+def test_gauss_matches_numpy(q):
+    x, w = quadrature.gauss(q)
+    xr, wr = npleg.leggauss(q)
+    np.testing.assert_allclose(x, xr, atol=2e-15)
+    np.testing.assert_allclose(w, wr, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("p", range(1, 12))
+def test_gll_exactness_degree(p):
+    """LGL with p+1 points is exact up to degree 2p-1 and not at 2p (Section 3)."""
+    x, w = quadrature.gll(p)
+    for m in range(2 * p):
+        exact = 2.0 / (m + 1) if m % 2 == 0 else 0.0
+        assert abs(np.sum(w * x ** m) - exact) < 1e-14
+    assert abs(np.sum(w * x ** (2 * p)) - 2.0 / (2 * p + 1)) > 1e-9
+    # interior nodes are the roots of P_p' (numpy's Legendre series, independent)
+    dP = npleg.legder(np.eye(p + 1)[p])
+    np.testing.assert_allclose(npleg.legval(x[1:-1], dP), 0.0, atol=1e-12 * p * p)
+
+
+@pytest.mark.parametrize("q", range(1, 12))
+def test_gauss_exactness_degree(q):
+    x, w = quadrature.gauss(q)
+    for m in range(2 * q):
+        exact = 2.0 / (m + 1) if m % 2 == 0 else 0.0
+        assert abs(np.sum(w * x ** m) - exact) < 1e-14
+    assert abs(np.sum(w * x ** (2 * q)) - 2.0 / (2 * q + 1)) > 1e-8
+
+
+# --- Lagrange basis -------------------------------------------------------------
+
+@pytest.mark.parametrize("p", range(1, 10))
+def test_lagrange_properties(p):
+    nodes, _ = quadrature.gll(p)
+    xs = np.linspace(-1, 1, 37)
+    L = basis.lagrange(nodes, xs)
+    D = basis.lagrange_deriv(nodes, xs)
+    np.testing.assert_allclose(L.sum(1), 1.0, atol=1e-13)
+    np.testing.assert_allclose(D.sum(1), 0.0, atol=1e-11 * p * p)
+    np.testing.assert_array_equal(basis.lagrange(nodes, nodes), np.eye(p + 1))
+    # interpolation and differentiation are exact on polynomials of degree p
+    c = np.arange(1, p + 2) / 7.0
+    f = npleg.legval(nodes, c)
+    np.testing.assert_allclose(L @ f, npleg.legval(xs, c), atol=1e-12)
+    np.testing.assert_allclose(D @ f, npleg.legval(xs, npleg.legder(c)), atol=1e-10 * p * p)
+
+
+@pytest.mark.parametrize("p", range(1, 10))
+def test_gll_derivative_closed_form(p):
+    """D_ij = P_p(x_i)/(P_p(x_j)(x_i-x_j)), D_00 = -p(p+1)/4, D_pp = p(p+1)/4,
+    0 otherwise (spectral-methods text cited in Section 3), with P_p from numpy."""
+    x, _ = quadrature.gll(p)
+    Pp = npleg.legval(x, np.eye(p + 1)[p])
+    ref = np.zeros((p + 1, p + 1))
+    for i in range(p + 1):
+        for j in range(p + 1):
+            if i != j:
+                ref[i, j] = Pp[i] / (Pp[j] * (x[i] - x[j]))
+    ref[0, 0] = -p * (p + 1) / 4.0
+    ref[p, p] = p * (p + 1) / 4.0
+    np.testing.assert_allclose(basis.lagrange_deriv(x, x), ref, atol=1e-12 * p * p)
+
+
+def test_1d_matrices_p2():
+    g = json.load(open(os.path.join(GOLD, "quadrature_closed_forms.json")))["matrices_p2"]
+    nodes, wl = quadrature.gll(2)
+    D = basis.lagrange_deriv(nodes, nodes)
+    K = D.T @ np.diag(wl) @ D
+    np.testing.assert_allclose(6 * K, g["gll_stiffness_times_6"], atol=1e-13)
+    xg, wg = quadrature.gauss(3)
+    B = basis.lagrange(nodes, xg)
+    np.testing.assert_allclose(15 * B.T @ np.diag(wg) @ B, g["gauss3_mass_times_15"], atol=1e-13)
+    np.testing.assert_allclose(3 * np.diag(wl), g["gll_mass_times_3"], atol=1e-14)
+
+
+# --- element matrices -----------------------------------------------------------
+
+def _ref_1d(p, kind, q=None):
+    nodes, _ = quadrature.gll(p)
+    pts, w = quadrature.rule(kind, p, q)
+    B = basis.lagrange(nodes, pts)
+    D = basis.lagrange_deriv(nodes, pts)
+    return B.T @ np.diag(w) @ B, D.T @ np.diag(w) @ D
+
+
+@pytest.mark.parametrize("p,kind,q", [(1, "gll", None), (2, "gll", None), (3, "gll", None),
+                                      (2, "gauss", 3), (3, "gauss", 5), (4, "gll", None)])
+def test_element_kronecker_closed_form(p, kind, q):
+    """Affine cube of side h, sigma = I: M_e = (h/2)^3 M1(x)M1(x)M1 and
+    K_e = (h/2) [M1(x)M1(x)K1 + M1(x)K1(x)M1 + K1(x)M1(x)M1] (x fastest)."""
+    h = 0.7
+    spec = synth.BoxSpec(p=p, n=(1, 1, 1), length=(h, h, h), quad=kind, nq1d=q or 0)
+    prob = operator.Problem(spec)
+    M, K = prob.elem_matrices(np.array([0]))
+    M1, K1 = _ref_1d(p, kind, q)
+    kr = np.kron
+    np.testing.assert_allclose(M[0], (h / 2) ** 3 * kr(M1, kr(M1, M1)), atol=1e-15)
+    Kref = (h / 2) * (kr(M1, kr(M1, K1)) + kr(M1, kr(K1, M1)) + kr(K1, kr(M1, M1)))
+    np.testing.assert_allclose(K[0], Kref, atol=1e-13)
+
+
+@pytest.mark.parametrize("p", range(1, 8))
+def test_sem_mass_lumping_is_sem_ni_mass(p):
+    """Row sums of the SEM (Gauss p+1) mass equal the SEM-NI diagonal mass on
+    affine elements (Section 3: the lumped SEM mass is the SEM-NI mass)."""
+    spec = synth.BoxSpec(p=p, n=(1, 1, 1), length=(1.3, 0.9, 1.1))
+    Mg, _ = operator.Problem(spec, quad="gauss", q=p + 1).elem_matrices(np.array([0]))
+    Ml, _ = operator.Problem(spec).elem_matrices(np.array([0]))
+    np.testing.assert_allclose(Mg[0].sum(1), np.diag(Ml[0]), rtol=1e-13)
+    np.testing.assert_allclose(Ml[0], np.diag(np.diag(Ml[0])), atol=1e-16)
+
+
+def test_q1_equivalences():
+    """Q1-SEM is Q1-FEM (exact mass (h/6)[[2,1],[1,2]] per axis); Q1-SEM-NI is
+    Q1-FEM with the trapezoidal rule (mass (h/2) I per axis) (Section 3)."""
+    h = 0.5
+    spec = synth.BoxSpec(p=1, n=(1, 1, 1), length=(h, h, h))
+    Mg, _ = operator.Problem(spec, quad="gauss", q=2).elem_matrices(np.array([0]))
+    Ml, _ = operator.Problem(spec).elem_matrices(np.array([0]))
+    m_fem = (h / 6) * np.array([[2, 1], [1, 2]])
+    m_trap = (h / 2) * np.eye(2)
+    kr = np.kron
+    np.testing.assert_allclose(Mg[0], kr(m_fem, kr(m_fem, m_fem)), atol=1e-16)
+    np.testing.assert_allclose(Ml[0], kr(m_trap, kr(m_trap, m_trap)), atol=1e-16)
+
+
+# --- global operator invariants -------------------------------------------------
+
+def _slab_small(p=3, quad="gll", q=0):
+    return synth.slab(p, (5, 3, 2), quad=quad, nq1d=q)
+
+
+@pytest.mark.parametrize("quad,q", [("gll", 0), ("gauss", 4), ("gauss", 5)])
+def test_global_invariants_sheared_slab(quad, q):
+    spec = _slab_small(3, quad, q)
+    prob = operator.Problem(spec)
+    A, M, K = prob.assemble()
+    ones = np.ones(prob.n_dof)
+    assert abs(A - A.T).max() < 1e-13 * abs(A).max()
+    assert np.max(np.abs(K @ ones)) < 1e-13 * abs(K).max()
+    # the shear keeps the volume 20*7*3 = 420 exactly for every p (the
+    # interpolated displacement vanishes at both ends of the slab)
+    assert abs(ones @ (M @ ones) - 420.0) < 1e-10
+
+
+def test_dirichlet_energy_of_linear_functions():
+    """u = c.x is in the isoparametric space; for constant isotropic sigma,
+    u^T K u = s |c|^2 |Omega| (here on the sheared slab)."""
+    spec = _slab_small(3).with_(fiber=False, sigma=(0.3, 0.3, 0.3))
+    prob = operator.Problem(spec)
+    _, _, K = prob.assemble()
+    c = np.array([0.3, -1.2, 0.7])
+    u = prob.mesh.xyz @ c
+    assert abs(u @ (K @ u) - 0.3 * (c @ c) * 420.0) < 1e-9 * 0.3 * (c @ c) * 420.0
+
+
+def _rotation(a, b, c):
+    Rz = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
+    Ry = np.array([[math.cos(b), 0, math.sin(b)], [0, 1, 0], [-math.sin(b), 0, math.cos(b)]])
+    Rx = np.array([[1, 0, 0], [0, math.cos(c), -math.sin(c)], [0, math.sin(c), math.cos(c)]])
+    return Rz @ Ry @ Rx
+
+
+@pytest.mark.parametrize("quad,q", [("gll", 0), ("gauss", 5)])
+def test_rotation_invariance(quad, q):
+    """Rotating coordinates and fibers together leaves K and M unchanged; a
+    swapped J^{-1}/J^{-T} or a wrong fiber contraction breaks this."""
+    spec = _slab_small(3, quad, q)
+    prob = operator.Problem(spec)
+    el = np.arange(spec.n_elem)
+    M0, K0 = prob.elem_matrices(el)
+    R = _rotation(0.4, -0.9, 1.3)
+    prob.mesh.xyz = prob.mesh.xyz @ R.T
+    prob.mesh.fiber = prob.mesh.fiber @ R.T
+    M1, K1 = prob.elem_matrices(el)
+    np.testing.assert_allclose(M1, M0, atol=1e-13 * abs(M0).max())
+    np.testing.assert_allclose(K1, K0, atol=1e-12 * abs(K0).max())
+
+
+def test_scaling():
+    """Scaling coordinates by s scales M by s^3 and K by s."""
+    spec = _slab_small(2)
+    prob = operator.Problem(spec)
+    el = np.arange(spec.n_elem)
+    M0, K0 = prob.elem_matrices(el)
+    prob.mesh.xyz = prob.mesh.xyz * 1.7
+    M1, K1 = prob.elem_matrices(el)
+    np.testing.assert_allclose(M1, 1.7 ** 3 * M0, rtol=1e-13, atol=1e-18)
+    np.testing.assert_allclose(K1, 1.7 * K0, rtol=1e-12, atol=1e-14)
+
+
+def test_r1_equals_r2_and_rows():
+    spec = _slab_small(3)
+    prob = operator.Problem(spec)
+    A, _, _ = prob.assemble()
+    x = synth.uniform(0, prob.n_dof)
+    y1 = A @ x
+    y2 = prob.apply_elementwise(x)
+    np.testing.assert_allclose(y2, y1, atol=1e-13 * np.abs(y1).max())
+    rows = np.array([0, 7, prob.n_dof // 2, prob.n_dof - 1, 123])
+    y3 = operator.apply_rows(spec, lambda g: x[g], rows)
+    np.testing.assert_allclose(y3, y1[rows], atol=1e-13 * np.abs(y1).max())
+    np.testing.assert_allclose(prob.diagonal(), A.diagonal(), rtol=1e-13)
+
+
+def test_spd_and_lanczos_bound():
+    spec = _slab_small(2)
+    prob = operator.Problem(spec)
+    A, _, _ = prob.assemble()
+    d = A.diagonal()
+    Ad = (A.multiply(1 / np.sqrt(d)[:, None]).multiply(1 / np.sqrt(d)[None, :])).tocsr()
+    ev = np.linalg.eigvalsh(Ad.toarray())
+    assert ev.min() > 0
+    lam = solvers.lanczos_lambda_max(A, 1 / d, synth.uniform(3, prob.n_dof), iters=10)
+    assert lam <= ev.max() * (1 + 1e-12)
+    assert lam >= 0.9 * ev.max()
+
+
+# --- solves ---------------------------------------------------------------------
+
+@pytest.mark.parametrize("p,kind,q,n,L", [
+    (2, "gll", None, (4, 4, 4), (1.0, 1.0, 1.0)),            # the tiny unit-cube workload
+    (3, "gll", None, (3, 2, 4), (1.3, 0.7, 2.1)),
+    (2, "gauss", 3, (2, 3, 2), (1.0, 2.0, 0.5)),
+    (3, "gauss", 5, (2, 2, 3), (0.8, 0.8, 1.5))])
+def test_fast_diagonalisation_matches_assembled_solve(p, kind, q, n, L):
+    spec = synth.BoxSpec(p=p, n=n, length=L, quad=kind, nq1d=q or 0, sigma=(0.6, 0.6, 0.6),
+                         alpha=1.7)
+    prob = operator.Problem(spec)
+    A, _, _ = prob.assemble()
+    b = synth.uniform(1, prob.n_dof)
+    x = spla.spsolve(A.tocsc(), b)
+    M1s, K1s = zip(*[solvers.assemble_1d(p, n[i], L[i], kind, q) for i in range(3)])
+    xf = solvers.fast_diag_solve(M1s, K1s, 1.7, 0.6, b)
+    np.testing.assert_allclose(x, xf, atol=1e-12 * np.abs(xf).max())
+
+
+@pytest.mark.parametrize("p,kind", [(3, "gll"), (4, "gll"), (3, "gauss"), (4, "gauss")])
+def test_exact_polynomial_reproduction(p, kind):
+    """u = g(x)+g(y)+g(z), g(t) = 3t^2-2t^3 (zero normal derivative on the unit
+    cube) is in Q_p for p >= 3 and every integral is exact, so the discrete
+    solution of alpha u - s Lap u = f equals u at the nodes."""
+    alpha, s = 1.7, 0.4
+    spec = synth.BoxSpec(p=p, n=(2, 3, 2), quad=kind, alpha=alpha, sigma=(s, s, s))
+    prob = operator.Problem(spec)
+    A, M, _ = prob.assemble()
+    g = lambda t: 3 * t ** 2 - 2 * t ** 3
+    u_fn = lambda X: g(X[..., 0]) + g(X[..., 1]) + g(X[..., 2])
+    f_fn = lambda X: alpha * u_fn(X) - s * ((6 - 12 * X[..., 0]) + (6 - 12 * X[..., 1]) + (6 - 12 * X[..., 2]))
+    b = load_vector(prob, f_fn)
+    x = spla.spsolve(A.tocsc(), b)
+    np.testing.assert_allclose(x, u_fn(prob.mesh.xyz), atol=1e-12)
+
+
+def load_vector(prob, f_fn):
+    """b_i = sum_e sum_k W|J| f(X(xi_k)) phi_i(xi_k), by the oracle's quadrature."""
+    nodes, _ = quadrature.gll(prob.p)
+    Phi, _ = basis.basis3(nodes, prob.pts)
+    map_nodes, _ = quadrature.gll(prob.map_p)
+    Phi_m, _ = basis.basis3(map_nodes, prob.pts)
+    b = np.zeros(prob.n_dof)
+    for el in prob.chunks():
+        geo = prob.elem_geometry(el)
+        Xq = np.einsum("eir,ki->ekr", prob.mesh.xyz[prob.mesh.elem_dof[el]], Phi_m)
+        be = np.einsum("ek,ki->ei", geo.WJ * f_fn(Xq), Phi)
+        np.add.at(b, prob.elem_dof[el].reshape(-1), be.reshape(-1))
+    return b
+
+
+def _warp(xyz, eps):
+    """Interior warping that keeps the unit cube's faces in place."""
+    s = np.sin(np.pi * xyz[:, 0]) * np.sin(np.pi * xyz[:, 1]) * np.sin(np.pi * xyz[:, 2])
+    return eps * np.stack([s, 0.7 * s, -0.5 * s], axis=1)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("p", [2, 3])
+def test_convergence_rate_curved(p):
+    """Manufactured u = cos(pi x)cos(pi y)cos(pi z) on a warped unit-cube mesh:
+    the nodal error decays like h^{p+1} (the SEM estimate of Section 3 gives
+    h^p in H1; the nodal/L2 error is one order higher)."""
+    alpha, s = 1.0, 1.0
+    u_fn = lambda X: np.cos(np.pi * X[..., 0]) * np.cos(np.pi * X[..., 1]) * np.cos(np.pi * X[..., 2])
+    f_fn = lambda X: (alpha + 3 * np.pi ** 2 * s) * u_fn(X)
+    errs = []
+    for n in (2, 4):
+        spec = synth.BoxSpec(p=p, n=(n, n, n), alpha=alpha, sigma=(s, s, s))
+        base = operator.Problem(spec)
+        prob = operator.Problem(spec, jitter=_warp(base.mesh.xyz, 0.04))
+        A, M, _ = prob.assemble()
+        x = spla.spsolve(A.tocsc(), load_vector(prob, f_fn))
+        e = x - u_fn(prob.mesh.xyz)
+        errs.append(math.sqrt(e @ (M @ e)))
+    rate = math.log2(errs[0] / errs[1])
+    assert rate > p + 1 - 0.6, (errs, rate)
+
+
+def test_p_convergence_is_faster_than_algebraic():
+    """Error at fixed h drops by large factors as p grows (Section 3)."""
+    alpha, s = 1.0, 1.0
+    u_fn = lambda X: np.cos(np.pi * X[..., 0]) * np.cos(np.pi * X[..., 1]) * np.cos(np.pi * X[..., 2])
+    f_fn = lambda X: (alpha + 3 * np.pi ** 2 * s) * u_fn(X)
+    errs = []
+    for p in (2, 3, 4, 5):
+        spec = synth.BoxSpec(p=p, n=(2, 2, 2), alpha=alpha, sigma=(s, s, s))
+        prob = operator.Problem(spec)
+        A, M, _ = prob.assemble()
+        x = spla.spsolve(A.tocsc(), load_vector(prob, f_fn))
+        e = x - u_fn(prob.mesh.xyz)
+        errs.append(math.sqrt(e @ (M @ e)))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(r > 4 for r in ratios), (errs, ratios)
+
+
+def test_paper_slab_dof_counts():
+    g = json.load(open(os.path.join(GOLD, "paper_slab_dofs.json")))
+    for p, n in g["dofs"].items():
+        spec = synth.BoxSpec(p=int(p), n=tuple(g["cells"]))
+        assert spec.n_dof == n
+        assert mesh.elem_dof_map(int(p), tuple(g["cells"])).max() + 1 == n if int(p) <= 2 else True
+
+
+def test_cg_matches_direct():
+    spec = _slab_small(3)
+    prob = operator.Problem(spec)
+    A, _, _ = prob.assemble()
+    b = synth.uniform(2, prob.n_dof)
+    xd = spla.spsolve(A.tocsc(), b)
+    x, it, rn = solvers.cg(A, b, rtol=1e-13)
+    np.testing.assert_allclose(x, xd, atol=1e-10 * np.abs(xd).max())
+
+
+# --- multigrid pieces -----------------------------------------------------------
+
+@pytest.mark.parametrize("pf,pc", [(4, 2), (2, 1), (7, 3), (3, 1)])
+def test_p_prolongation_reproduces_polynomials(pf, pc):
+    n = (2, 3, 2)
+    P = multigrid.prolongation_p(n, pf, pc)
+    Xf = mesh.box(synth.BoxSpec(p=pf, n=n)).xyz
+    Xc = mesh.box(synth.BoxSpec(p=pc, n=n)).xyz
+    f = lambda X: (X[:, 0] ** pc) * (1 + X[:, 1]) ** pc - 2 * X[:, 2] ** pc + X[:, 0] * X[:, 1] * X[:, 2]
+    np.testing.assert_allclose(P @ f(Xc), f(Xf), atol=1e-12)
+    assert abs(P.sum(1).A1 - 1).max() < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_h_prolongation_reproduces_polynomials(p):
+    nf = (4, 2, 6)
+    P = multigrid.prolongation_h(nf, p)
+    Xf = mesh.box(synth.BoxSpec(p=p, n=nf)).xyz
+    Xc = mesh.box(synth.BoxSpec(p=p, n=(2, 1, 3))).xyz
+    f = lambda X: (X[:, 0] ** p) * (1 + X[:, 1]) ** p - 2 * X[:, 2] ** p + X[:, 0] * X[:, 2]
+    if p == 1:
+        f = lambda X: 1 + X[:, 0] - 2 * X[:, 1] + 3 * X[:, 2]
+    np.testing.assert_allclose(P @ f(Xc), f(Xf), atol=1e-12)
+
+
+def test_galerkin_identity_p_levels():
+    """Affine mesh, exact (Gauss) quadrature: A_c = P^T A_f P."""
+    spec = synth.BoxSpec(p=4, n=(2, 2, 1), length=(1.0, 0.6, 0.9), quad="gauss", nq1d=5,
+                         sigma=(0.5, 0.5, 0.5), alpha=2.0)
+    Af, _, _ = operator.Problem(spec).assemble()
+    Ac, _, _ = operator.Problem(spec, dof_p=2, quad="gauss", q=3).assemble()
+    P = multigrid.prolongation_p(spec.n, 4, 2)
+    np.testing.assert_allclose((P.T @ Af @ P).toarray(), Ac.toarray(), atol=1e-12)
+
+
+def _chebyshev_T(k, x):
+    return np.cosh(k * np.arccosh(x)) if x >= 1 else np.cos(k * np.arccos(x))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_chebyshev_error_polynomial(k):
+    """From x0 = 0 with D = I, the error in each eigencomponent is multiplied by
+    T_k((theta - lam)/delta) / T_k(theta/delta) (closed form)."""
+    lam = np.linspace(0.05, 2.0, 40)
+    A = np.diag(lam)
+    xs = synth.uniform(5, 40)
+    b = A @ xs
+    lmax = 2.0
+    x = solvers.chebyshev(A, np.ones(40), b, None, lmax, k)
+    lo, hi = 0.08 * lmax * 1.0, 1.2 * lmax
+    th, de = (hi + lo) / 2, (hi - lo) / 2
+    fac = np.array([_chebyshev_T(k, (th - l) / de) for l in lam]) / _chebyshev_T(k, th / de)
+    np.testing.assert_allclose(xs - x, fac * xs, atol=1e-13)
+
+
+def test_vcycle_is_symmetric_positive():
+    spec = synth.slab(4, (4, 2, 2))
+    levels, transfers = [], []
+    for pl in (4, 2, 1):
+        prob = operator.Problem(spec, dof_p=pl)
+        A, _, _ = prob.assemble()
+        dinv = 1 / A.diagonal()
+        lam = solvers.lanczos_lambda_max(A, dinv, synth.uniform(9, prob.n_dof))
+        levels.append((A, dinv, lam))
+    transfers = [multigrid.prolongation_p(spec.n, 4, 2), multigrid.prolongation_p(spec.n, 2, 1)]
+    N = levels[0][0].shape[0]
+    V = lambda r: solvers.vcycle(levels, transfers, r, 3, 6)
+    b1, b2 = synth.uniform(10, N), synth.uniform(11, N)
+    assert abs(V(b1) @ b2 - b1 @ V(b2)) < 1e-12 * abs(V(b1) @ b2)
+    assert V(b1) @ b1 > 0
+    # as a preconditioner it converges fast and to the direct solution
+    A = levels[0][0]
+    x, it, _ = solvers.cg(A, b1, rtol=1e-12, M=V)
+    np.testing.assert_allclose(x, spla.spsolve(A.tocsc(), b1), atol=1e-9 * abs(x).max())
+    assert it < 25
+
+
+# --- adjoint --------------------------------------------------------------------
+
+def test_linearity_in_sigma_and_adjoint_fd():
+    spec = synth.slab(2, (3, 2, 2))
+    sig = synth.element_sigma(4, 1, spec.n_elem)[0]
+    sig[:, 2] = sig[:, 1] * 1.3  # distinct sigma_n exercises the no-sheet reading
+    prob = operator.Problem(spec, sigma=sig)
+    f = synth.uniform(5, prob.n_dof)
+    ut = synth.uniform(6, prob.n_dof) * 0.01
+    L, g, lam, u = adjoint.loss_and_grad(prob, f, ut)
+    h = 1e-6
+    for e, c in [(0, 0), (5, 1), (11, 0), (7, 1)]:
+        sp_, sm_ = sig.copy(), sig.copy()
+        sp_[e, c] += h
+        sm_[e, c] -= h
+        Lp = adjoint.loss(operator.Problem(spec, sigma=sp_), f, ut)
+        Lm = adjoint.loss(operator.Problem(spec, sigma=sm_), f, ut)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - g[e, c]) <= 1e-6 * max(abs(fd), 1e-3 * abs(g).max()), (e, c, fd, g[e, c])
+    # without a sheet sigma_n does not enter
+    assert np.all(g[:, 2] == 0)
+    # A is exactly linear in sigma: A(2 sigma) - A(sigma) = K(sigma)
+    A1, _, K1 = prob.assemble()
+    A2, _, _ = operator.Problem(spec, sigma=2 * sig).assemble()
+    assert abs((A2 - A1) - K1).max() < 1e-12 * abs(K1).max()
+
+
+# --- ionic ----------------------------------------------------------------------
+
+def test_aliev_panfilov_rest_and_rates():
+    prm = synth.AP_PARAMS
+    F, G = ionic.ap_rates(np.array([0.0]), np.array([0.0]), **prm)
+    assert F[0] == 0.0 and G[0] == 0.0
+    # hand evaluation at u = 0.5, w = 0.1
+    u, w = 0.5, 0.1
+    k, a = prm["k"], prm["a"]
+    Fh = k * 0.5 * 0.5 * 0.35 - 0.05
+    eps = prm["eps0"] + prm["mu1"] * 0.1 / 0.8
+    Gh = eps * (-0.1 - k * 0.5 * (0.5 - 0.15 - 1))
+    F, G = ionic.ap_rates(np.array([u]), np.array([w]), **prm)
+    assert abs(F[0] - Fh) < 1e-15 and abs(G[0] - Gh) < 1e-15
+    V = np.array([prm["v_rest"]])
+    b, wn = ionic.imex_rhs_and_gate(V, np.zeros(1), np.zeros(1), np.array([2.0]), 0.05,
+                                    synth.CHI, synth.CM, prm)
+    assert abs(b[0] - 2.0 * (synth.CHI * synth.CM / 0.05) * prm["v_rest"]) < 1e-12
+    assert wn[0] == 0.0
