@@ -1,0 +1,284 @@
+/*
+ * mfsem.h -- C ABI of the matrix-free spectral-element monodomain operator for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * What it computes (arXiv 2205.05136):
+ *   A = alpha*M + K(sigma), the implicit operator of the monodomain linear
+ *   system (Section 3, the linear system; the paper has alpha = 3/(2 dt) with
+ *   chi = Cm = 1), on conforming hexahedral meshes of degree p, with the
+ *   diffusion tensor sigma = sigma_l f f^T + sigma_t s s^T + sigma_n n n^T
+ *   (Section 2), applied matrix-free with sum factorisation (Section 4.1),
+ *   either with GLL quadrature collocated with the nodes (SEM-NI, diagonal mass)
+ *   or with Legendre-Gauss quadrature (SEM) (Section 3); a preconditioned CG
+ *   (Section 4) with a matrix-free geometric multigrid V-cycle whose smoother
+ *   is Chebyshev-Jacobi with a CG/Lanczos estimate of lambda_max, and whose
+ *   levels are linked by p- and octree h-interpolation and its transpose
+ *   (Section 4.3; parameters from Section 5).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments marked [device] are HIP device pointers owned by the
+ *     caller; [host] marks host memory.  Scalars are passed by value.
+ *   - The library never allocates device memory.  Objects that need device
+ *     storage take a caller-provided workspace `ws` of at least the size the
+ *     matching *_workspace_bytes query returns, aligned to 256 bytes; the
+ *     object keeps pointers into it, so `ws` must outlive the object.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call is enqueued on `stream` and returns without synchronising,
+ *     except those marked [sync], which wait for `stream` before returning.
+ *   - Return value: MFSEM_OK or a negative mfsem_status.  On failure
+ *     mfsem_last_error() returns a message (thread-local, valid until the next
+ *     failing call on the same thread).  Arguments are validated on the host
+ *     before any launch; a failed call leaves outputs untouched unless stated.
+ *   - Vectors with a batch dimension are laid out [batch][n_dof], contiguous.
+ *   - Local node numbering inside an element is i = a + P*(b + P*c), P = p+1,
+ *     a along the first reference axis (fastest).
+ */
+#ifndef MFSEM_H
+#define MFSEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MFSEM_ABI_VERSION 1
+#define MFSEM_MAX_P 8
+
+typedef enum {
+  MFSEM_OK = 0,
+  MFSEM_EINVAL = -1,        /* invalid argument (null pointer, size, range, alignment) */
+  MFSEM_EUNSUPPORTED = -2,  /* valid but not implemented (e.g. a degree above MFSEM_MAX_P) */
+  MFSEM_EGEOMETRY = -3,     /* det J <= 0 at some quadrature point (message names it) */
+  MFSEM_EDEVICE = -4,       /* a HIP runtime or launch error */
+  MFSEM_ENOCONV = -5,       /* iteration limit reached before the tolerance */
+  MFSEM_EBREAKDOWN = -6,    /* p^T A p <= 0 or (r, z) <= 0 in (P)CG */
+  MFSEM_ENONFINITE = -7     /* NaN or Inf met in a residual norm */
+} mfsem_status;
+
+typedef enum { MFSEM_GLL = 0, /* SEM-NI */ MFSEM_GAUSS = 1 /* SEM */ } mfsem_quad;
+typedef enum { MFSEM_F64 = 0, MFSEM_F32 = 1 } mfsem_dtype;
+typedef enum { MFSEM_TRANSFER_P = 0, MFSEM_TRANSFER_H = 1 } mfsem_transfer_kind;
+
+typedef struct mfsem_op mfsem_op;
+typedef struct mfsem_mg mfsem_mg;
+
+/* ABI version (MFSEM_ABI_VERSION of the built library). */
+int mfsem_abi_version(void);
+
+/* Message of the last failing call on this thread ("" if none). [host] */
+const char* mfsem_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Mesh setup: structured boxes (Section 3: conforming hexahedral meshes and
+ * the Q_p space with nodes at the GLL points of each element).
+ *
+ * The (p*n[0]+1) x (p*n[1]+1) x (p*n[2]+1) node lattice has global index
+ * g = I + NX*(J + NY*K); element (ex,ey,ez) has index ex + n0*(ey + n1*ez).
+ * Nodes inside an element sit at the GLL points of the element's edges.
+ * If shear_amp != 0 every node (x,y,z) moves to (x+d, y+d, z+d) with
+ * d = shear_amp * (length[0]/n[0]) * sin(2*pi*(x - origin[0])/length[0]).
+ * If fiber != 0 the fiber at a node is (cos t, sin t, 0) with t going linearly
+ * from theta0 at z = origin[2] to theta1 at z = origin[2] + length[2]
+ * (undeformed z).                                                            */
+typedef struct {
+  int32_t p;            /* 1..MFSEM_MAX_P */
+  int32_t n[3];         /* elements per axis, >= 1 */
+  double origin[3];
+  double length[3];     /* > 0 */
+  double shear_amp;
+  int32_t fiber;        /* 0 or 1 */
+  double theta0, theta1;/* radians */
+} mfsem_box_desc;
+
+/* Element and node counts of a box. [host] */
+mfsem_status mfsem_box_counts(const mfsem_box_desc* box, int64_t* n_elem, int64_t* n_dof);
+
+/* Fill elem_dof [n_elem][(p+1)^3] (int32), xyz [n_dof][3] and, if box->fiber,
+ * fiber [n_dof][3] (may be NULL otherwise).  All [device], caller-sized from
+ * mfsem_box_counts.  EINVAL if n_dof exceeds INT32_MAX.                     */
+mfsem_status mfsem_box_generate(const mfsem_box_desc* box, int32_t* elem_dof, double* xyz,
+                                double* fiber, void* stream);
+
+/* Octree parents for a box of n_fine[3] elements (all even) coarsened to
+ * n_fine/2: parent[e] = coarse element containing fine element e, child[e] =
+ * cx | cy<<1 | cz<<2 with c* the fine element's offset (0/1) inside its parent
+ * along each axis.  [device] int32 parent[n_elem_fine], int8 child[n_elem_fine]. */
+mfsem_status mfsem_box_parents(const int32_t n_fine[3], int32_t* parent, int8_t* child,
+                               void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Operator A = alpha*M + K(sigma).
+ *
+ * DOF space: degree p, numbering elem_dof.  Geometry: the isoparametric map of
+ * degree map_p through map_xyz at the nodes map_elem_dof (a p-coarsened
+ * multigrid level keeps the fine map with a coarser DOF space).  At each
+ * quadrature point the fiber (and sheet) are interpolated with the map basis
+ * and normalised (the sheet is made orthogonal to the fiber, n = f x s); sigma
+ * is sigma_t I + (sigma_l - sigma_t) f f^T without a sheet, the full
+ * orthotropic tensor with one, and sigma_t I without a fiber.
+ * Set-up computes and stores, in FP64 (and/or FP32), per element and
+ * quadrature point, G = W |J| J^{-1} sigma J^{-T} (6 values) and W |J|.      */
+typedef struct {
+  int32_t p;                   /* DOF degree, 1..MFSEM_MAX_P */
+  int32_t quad;                /* mfsem_quad */
+  int32_t nq1d;                /* points per axis: GLL needs p+1; GAUSS p+1..p+3; 0 = p+1 */
+  int64_t n_elem;
+  int64_t n_dof;               /* number of global DOFs (<= INT32_MAX) */
+  const int32_t* elem_dof;     /* [device] [n_elem][(p+1)^3]; referenced until destroy */
+  int32_t map_p;               /* geometry degree, 1..MFSEM_MAX_P (0 = p) */
+  const int32_t* map_elem_dof; /* [device] [n_elem][(map_p+1)^3]; NULL = elem_dof (map_p == p) */
+  int64_t n_map_nodes;         /* rows of map_xyz / fiber / sheet */
+  const double* map_xyz;       /* [device] [n_map_nodes][3]; referenced until destroy */
+  const double* fiber;         /* [device] [n_map_nodes][3] or NULL; referenced until destroy */
+  const double* sheet;         /* [device] [n_map_nodes][3] or NULL (needs fiber) */
+  const double* sigma;         /* [device] [batch][n_elem][3] (sigma_l, sigma_t, sigma_n) or NULL */
+  double sigma_const[3];       /* used when sigma == NULL */
+  int32_t batch;               /* >= 1 parameter sets; vectors become [batch][n_dof] */
+  double alpha;                /* mass coefficient, >= 0 */
+  int32_t store_f64;           /* build FP64 geometry (needed by FP64 calls) */
+  int32_t store_f32;           /* build FP32 geometry (needed by FP32 calls) */
+} mfsem_op_desc;
+
+/* Workspace an operator needs. [host] */
+mfsem_status mfsem_op_workspace_bytes(const mfsem_op_desc* d, size_t* bytes);
+
+/* Create an operator: validates `d`, runs the geometry kernel and checks
+ * det J > 0 everywhere (EGEOMETRY names the first bad element and point).
+ * sigma is read during this call only.  [sync]                               */
+mfsem_status mfsem_op_create(const mfsem_op_desc* d, void* ws, size_t ws_bytes, void* stream,
+                             mfsem_op** out);
+
+/* Release the host handle (NULL-safe); the workspace belongs to the caller. */
+mfsem_status mfsem_op_destroy(mfsem_op* op);
+
+/* Change alpha (host-side, takes effect for later calls). */
+mfsem_status mfsem_op_set_alpha(mfsem_op* op, double alpha);
+
+/* Replace the per-element conductivities [device][batch][n_elem][3] and
+ * recompute the stored geometry. [sync]                                      */
+mfsem_status mfsem_op_set_sigma(mfsem_op* op, const double* sigma, void* stream);
+
+/* y = A x for every batch member; x, y [device][batch][n_dof] of `dtype`.
+ * x and y must not overlap.  (Section 4: the matrix-vector product inside
+ * CG; Alg. 1's cell loop, with the sum factorisation of Section 4.1.)        */
+mfsem_status mfsem_op_apply(const mfsem_op* op, int32_t dtype, const void* x, void* y,
+                            void* stream);
+
+/* y = M x (the mass matrix alone, same quadrature). */
+mfsem_status mfsem_op_apply_mass(const mfsem_op* op, int32_t dtype, const void* x, void* y,
+                                 void* stream);
+
+/* d = diag(A) [device][batch][n_dof] (the point-Jacobi part of the
+ * Chebyshev smoother, Section 4.3).                                          */
+mfsem_status mfsem_op_diagonal(const mfsem_op* op, int32_t dtype, void* d, void* stream);
+
+/* g[b][e][c] = w_b^T (dA/dsigma_{e,c}) u_b for c = (l, t, n): the derivative
+ * of A with respect to each element's conductivities contracted with two
+ * vectors (FP64).  Without a sheet, c = t covers the whole plane normal to the
+ * fiber and g[..][2] = 0; without a fiber only c = t is non-zero.
+ * u, w [device][batch][n_dof]; g [device][batch][n_elem][3].                  */
+mfsem_status mfsem_op_grad_sigma(const mfsem_op* op, const double* u, const double* w,
+                                 double* g, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Geometric multigrid V-cycle (Section 4.3).  Levels are operators created by
+ * the caller, finest first; transfers[l] links level l (fine) and l+1.
+ * P-transfers keep the elements and lower the degree; H-transfers map each
+ * fine element to its octree parent.  Prolongation interpolates the coarse
+ * function at the fine nodes; restriction is its exact transpose.  Smoothing
+ * is Chebyshev-Jacobi of `degree` on [lo_frac, hi_frac] * lambda_max, with
+ * lambda_max from `eig_iters` Jacobi-CG steps on a seeded start vector
+ * (Section 5: 10 steps, [0.08, 1.2]); the coarsest level is a Chebyshev
+ * smoothing of `coarse_degree` from zero.  The cycle is symmetric, so it is a
+ * valid CG preconditioner.  Every level must hold geometry in `precision`.  */
+typedef struct {
+  int32_t kind;             /* mfsem_transfer_kind */
+  const int32_t* parent;    /* H: [device] [n_elem_fine]; P: NULL */
+  const int8_t* child;      /* H: [device] [n_elem_fine]; P: NULL */
+} mfsem_transfer_desc;
+
+typedef struct {
+  int32_t n_levels;                      /* 1..16 */
+  const mfsem_op* const* ops;            /* [host] [n_levels] */
+  const mfsem_transfer_desc* transfers;  /* [host] [n_levels-1] */
+  int32_t degree;                        /* >= 1 */
+  int32_t coarse_degree;                 /* >= 1 */
+  double lo_frac, hi_frac;               /* 0 < lo < hi */
+  int32_t eig_iters;                     /* >= 1 */
+  uint64_t eig_seed;
+  const double* lambda_max;              /* [host] [n_levels][batch] or NULL = estimate */
+  int32_t precision;                     /* mfsem_dtype of the whole cycle */
+} mfsem_mg_desc;
+
+mfsem_status mfsem_mg_workspace_bytes(const mfsem_mg_desc* d, size_t* bytes);
+
+/* Build the hierarchy: diagonals, lambda_max estimates, transfer data. [sync] */
+mfsem_status mfsem_mg_create(const mfsem_mg_desc* d, void* ws, size_t ws_bytes, void* stream,
+                             mfsem_mg** out);
+mfsem_status mfsem_mg_destroy(mfsem_mg* mg);
+
+/* z = V(r): one V-cycle from a zero guess.  r, z [device][batch][n_dof] in
+ * the cycle's precision.  Uses buffers inside the workspace: calls on the
+ * same mg must not overlap.                                                 */
+mfsem_status mfsem_mg_vcycle(const mfsem_mg* mg, const void* r, void* z, void* stream);
+
+/* lambda_max per level and batch member, [host] [n_levels][batch]. */
+mfsem_status mfsem_mg_lambdas(const mfsem_mg* mg, double* lam);
+
+/* One transfer between levels `level` (fine) and `level`+1 (coarse), in the
+ * cycle's precision, [device] [batch][n_dof of the level]:
+ *   direction 0 (prolongation): out_fine = P in_coarse (every fine DOF written);
+ *   direction 1 (restriction):  out_coarse = P^T in_fine (out is overwritten). */
+mfsem_status mfsem_mg_transfer(const mfsem_mg* mg, int32_t level, int32_t direction,
+                               const void* in, void* out, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Preconditioned CG in FP64 (Section 4).  mg == NULL: plain CG.  An FP32 mg
+ * is applied to an FP32 copy of r and its result widened; use flexible = 1
+ * then (Polak-Ribiere beta).  Stops each batch member when
+ * ||r||_2 <= max(rtol*||b||_2, atol) (true recurrence residual, l2 norm).   */
+typedef struct {
+  double rtol, atol;
+  int32_t max_it;     /* >= 1 */
+  int32_t flexible;   /* 0/1 */
+} mfsem_solve_opts;
+
+typedef struct {
+  int32_t iters;
+  int32_t status;     /* mfsem_status of this batch member */
+  double r0_norm, r_norm, b_norm;
+} mfsem_solve_info;
+
+mfsem_status mfsem_pcg_workspace_bytes(const mfsem_op* op, const mfsem_mg* mg, size_t* bytes);
+
+/* Solve A x = b.  b, x [device][batch][n_dof] FP64; x holds the initial
+ * guess on entry and the last iterate on exit.  info [host][batch].
+ * Returns the worst member status (ENOCONV, EBREAKDOWN, ENONFINITE). [sync] */
+mfsem_status mfsem_pcg(const mfsem_op* op, const mfsem_mg* mg, const double* b, double* x,
+                       const mfsem_solve_opts* opts, mfsem_solve_info* info, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Pointwise ionic step for the full monodomain time loop (the DOF-wise ionic
+ * loop and right-hand side of Alg. 1, first-order IMEX in place of BDF2, with
+ * the two-variable Aliev-Panfilov model in place of the paper's ionic
+ * models).  With u = (V - v_rest)/v_amp:
+ *   F = k u (1-u)(u-a) - u w,   G = (eps0 + mu1 w/(u+mu2)) (-w - k u (u-a-1))
+ *   b = mass_diag * (chi*cm/dt * V + chi*cm*(v_amp/t_scale)*F + i_stim)
+ *   w <- w + (dt/t_scale) G
+ * All arrays [device][n] FP64; i_stim may be NULL (zero).                    */
+typedef struct {
+  double k, a, eps0, mu1, mu2, v_rest, v_amp, t_scale;
+} mfsem_ap_params;
+
+mfsem_status mfsem_ap_imex_rhs(int64_t n, double dt, double chi, double cm,
+                               const mfsem_ap_params* prm, const double* V, double* w,
+                               const double* i_stim, const double* mass_diag, double* b,
+                               void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFSEM_H */

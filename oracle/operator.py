@@ -99,18 +99,29 @@ def element_matrices(geo: Geometry, sig_e, dof_p, pts, alpha, parts=False):
     sig_e [E, 3].  With parts=True also returns dK/dsigma_{l,t,n} [3, E, P^3, P^3]."""
     nodes, _ = quadrature.gll(dof_p)
     Phi, dPhi = basis.basis3(nodes, pts)                      # [Q3, P3], [3, Q3, P3]
-    grad = np.einsum("eksr,ski->ekri", geo.Jinv, dPhi)        # J^{-T} grad_ref
     E, Q3 = geo.WJ.shape
-    M = np.einsum("ek,ki,kj->eij", geo.WJ, Phi, Phi)
+    P3 = Phi.shape[1]
+    # physical gradients grad[e,k,r,i] = sum_s Jinv[e,k,s,r] dPhi[s,k,i]  (J^{-T} grad_ref)
+    grad = np.zeros((E, Q3, 3, P3))
+    for s_ in range(3):
+        grad += geo.Jinv[:, :, s_, :, None] * dPhi[s_][None, :, None, :]
+    # M_e = Phi^T diag(W|J|) Phi
+    M = np.matmul(Phi.T[None, :, :] * geo.WJ[:, None, :], Phi[None, :, :])
     sig = sigma_tensor(np.broadcast_to(sig_e[:, None, :], (E, Q3, 3)), geo.f, geo.s)
-    Sg = np.einsum("ekrs,eksj->ekrj", sig, grad)
-    K = np.einsum("ek,ekri,ekrj->eij", geo.WJ, grad, Sg)
+
+    def stiffness(T):
+        # K_e[i,j] = sum_k sum_r grad[k,r,i] (W|J| T grad)[k,r,j], as one matmul per element
+        Tg = np.zeros_like(grad)
+        for s_ in range(3):
+            Tg += T[:, :, :, s_, None] * grad[:, :, s_, None, :]
+        Tg *= geo.WJ[:, :, None, None]
+        return np.matmul(grad.reshape(E, 3 * Q3, P3).transpose(0, 2, 1),
+                         Tg.reshape(E, 3 * Q3, P3))
+
+    K = stiffness(sig)
     if not parts:
         return M, K
-    dK = []
-    for T in sigma_parts(geo.f, geo.s, (E, Q3)):
-        Tg = np.einsum("ekrs,eksj->ekrj", T, grad)
-        dK.append(np.einsum("ek,ekri,ekrj->eij", geo.WJ, grad, Tg))
+    dK = [stiffness(T) for T in sigma_parts(geo.f, geo.s, (E, Q3))]
     return M, K, np.stack(dK)
 
 

@@ -1,0 +1,463 @@
+// The C ABI of libmfsem: argument validation, error reporting and dispatch.
+// No C++ exception crosses this boundary; every entry point returns a status.
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "solver.hpp"
+
+namespace mfsem {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+void fail(mfsem_status code, const std::string& msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess)
+    fail(MFSEM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void launch_box(const mfsem_box_desc& d, int64_t n_elem, int64_t n_dof, const double* xi_host,
+                int32_t* ed, double* xyz, double* fib, hipStream_t s);
+void launch_box_parents(const int32_t n[3], int32_t* parent, int8_t* child, hipStream_t s);
+void launch_ap(int64_t n, double dt, double chi, double cm, const mfsem_ap_params& prm,
+               const double* V, double* w, const double* istim, const double* m, double* b,
+               hipStream_t s);
+
+namespace {
+
+template <typename F>
+mfsem_status guarded(F&& f) {
+  try {
+    f();
+    return MFSEM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal error: ") + e.what());
+    return MFSEM_EDEVICE;
+  }
+}
+
+void require(bool ok, const std::string& msg) {
+  if (!ok) fail(MFSEM_EINVAL, msg);
+}
+
+void require_aligned(const void* p, size_t a, const char* what) {
+  require((reinterpret_cast<uintptr_t>(p) % a) == 0,
+          std::string(what) + " is not " + std::to_string(a) + "-byte aligned");
+}
+
+void box_counts(const mfsem_box_desc* b, int64_t* ne, int64_t* nd) {
+  require(b != nullptr, "box descriptor is NULL");
+  require(b->p >= 1 && b->p <= MFSEM_MAX_P, "box p must be in 1..MFSEM_MAX_P");
+  for (int i = 0; i < 3; ++i) {
+    require(b->n[i] >= 1, "box element counts must be >= 1");
+    require(b->length[i] > 0.0 && std::isfinite(b->length[i]), "box lengths must be positive");
+  }
+  *ne = (int64_t)b->n[0] * b->n[1] * b->n[2];
+  *nd = ((int64_t)b->p * b->n[0] + 1) * ((int64_t)b->p * b->n[1] + 1) * ((int64_t)b->p * b->n[2] + 1);
+}
+
+void validate_op(const mfsem_op_desc* d) {
+  require(d != nullptr, "operator descriptor is NULL");
+  require(d->p >= 1 && d->p <= MFSEM_MAX_P, "p must be in 1..MFSEM_MAX_P");
+  require(d->quad == MFSEM_GLL || d->quad == MFSEM_GAUSS, "quad must be MFSEM_GLL or MFSEM_GAUSS");
+  const int q = d->nq1d == 0 ? d->p + 1 : d->nq1d;
+  if (d->quad == MFSEM_GLL) require(q == d->p + 1, "GLL quadrature needs nq1d == p+1");
+  else require(q >= d->p + 1 && q <= d->p + 3, "Gauss quadrature needs p+1 <= nq1d <= p+3");
+  const int mp = d->map_p == 0 ? d->p : d->map_p;
+  require(mp >= 1 && mp <= MFSEM_MAX_P, "map_p must be in 1..MFSEM_MAX_P");
+  require(d->map_elem_dof != nullptr || mp == d->p, "map_elem_dof may be NULL only when map_p == p");
+  require(d->n_elem >= 0 && d->n_dof >= 0, "negative sizes");
+  require(d->n_dof <= INT32_MAX, "n_dof must fit in int32");
+  require(d->n_elem <= INT32_MAX, "n_elem must fit in int32");
+  require(d->n_elem == 0 || d->elem_dof != nullptr, "elem_dof is NULL");
+  require(d->n_elem == 0 || d->map_xyz != nullptr, "map_xyz is NULL");
+  require(d->sheet == nullptr || d->fiber != nullptr, "a sheet field needs a fiber field");
+  require(d->batch >= 1 && d->batch <= 65535, "batch must be in 1..65535");
+  require(d->alpha >= 0.0 && std::isfinite(d->alpha), "alpha must be finite and >= 0");
+  require(d->store_f64 || d->store_f32, "store_f64 or store_f32 must be set");
+  if (!d->sigma)
+    for (int i = 0; i < 3; ++i)
+      require(std::isfinite(d->sigma_const[i]), "sigma_const must be finite");
+}
+
+void op_init(mfsem_op& op, const mfsem_op_desc* d) {
+  op.d = *d;
+  op.P = d->p + 1;
+  op.Q = d->nq1d == 0 ? d->p + 1 : d->nq1d;
+  op.d.nq1d = op.Q;
+  op.d.map_p = d->map_p == 0 ? d->p : d->map_p;
+  op.Pm = op.d.map_p + 1;
+  op.nq3 = (int64_t)op.Q * op.Q * op.Q;
+  op.alpha = d->alpha;
+  op.off = table_offsets(op.P, op.Q, op.Pm);
+}
+
+void check_op(const mfsem_op* op, int dtype) {
+  require(op != nullptr, "operator is NULL");
+  require(dtype == MFSEM_F64 || dtype == MFSEM_F32, "dtype must be MFSEM_F64 or MFSEM_F32");
+  if (dtype == MFSEM_F64) require(op->G64 != nullptr, "operator has no FP64 geometry (store_f64 = 0)");
+  else require(op->G32 != nullptr, "operator has no FP32 geometry (store_f32 = 0)");
+}
+
+void read_bad_flag(const mfsem_op& op, hipStream_t s) {
+  unsigned long long bad = 0;
+  MFSEM_HIP(hipMemcpyAsync(&bad, op.bad, sizeof(bad), hipMemcpyDeviceToHost, s));
+  MFSEM_HIP(hipStreamSynchronize(s));
+  if (bad != ~0ull) {
+    const unsigned long long e = bad / op.nq3, k = bad % op.nq3;
+    fail(MFSEM_EGEOMETRY, "det J <= 0 in element " + std::to_string(e) + " at quadrature point " +
+                              std::to_string(k));
+  }
+}
+
+}  // namespace
+
+void op_layout(mfsem_op& op, Arena& a) {
+  const size_t ne = (size_t)op.d.n_elem, nq = (size_t)op.nq3, B = (size_t)op.d.batch;
+  if (op.d.store_f64) {
+    op.G64 = a.take_n<double>(B * ne * 6 * nq);
+    op.WJ64 = a.take_n<double>(ne * nq);
+  }
+  if (op.d.store_f32) {
+    op.G32 = a.take_n<float>(B * ne * 6 * nq);
+    op.WJ32 = a.take_n<float>(ne * nq);
+  }
+  op.tab64 = a.take_n<double>(op.off.total);
+  op.tab32 = a.take_n<float>(op.off.total);
+  op.bad = a.take_n<unsigned long long>(1);
+  op.sigma_copy = op.d.sigma ? a.take_n<double>(B * ne * 3) : nullptr;
+}
+
+}  // namespace mfsem
+
+using namespace mfsem;
+
+extern "C" {
+
+int mfsem_abi_version(void) { return MFSEM_ABI_VERSION; }
+
+const char* mfsem_last_error(void) { return mfsem::g_last_error.c_str(); }
+
+mfsem_status mfsem_box_counts(const mfsem_box_desc* box, int64_t* n_elem, int64_t* n_dof) {
+  return guarded([&] {
+    require(n_elem && n_dof, "output pointers are NULL");
+    box_counts(box, n_elem, n_dof);
+  });
+}
+
+mfsem_status mfsem_box_generate(const mfsem_box_desc* box, int32_t* elem_dof, double* xyz,
+                                double* fiber, void* stream) {
+  return guarded([&] {
+    int64_t ne, nd;
+    box_counts(box, &ne, &nd);
+    require(nd <= INT32_MAX, "box has more than INT32_MAX nodes");
+    require(elem_dof && xyz, "elem_dof or xyz is NULL");
+    require(!box->fiber || fiber, "fiber output is NULL but box->fiber is set");
+    hipStream_t s = as_stream(stream);
+    // GLL points of degree p for the node placement (passed by value)
+    std::vector<double> xi, w;
+    gll_rule(box->p, xi, w);
+    launch_box(*box, ne, nd, xi.data(), elem_dof, xyz, fiber, s);
+  });
+}
+
+mfsem_status mfsem_box_parents(const int32_t n_fine[3], int32_t* parent, int8_t* child,
+                               void* stream) {
+  return guarded([&] {
+    require(n_fine && parent && child, "NULL argument");
+    for (int i = 0; i < 3; ++i)
+      require(n_fine[i] >= 2 && n_fine[i] % 2 == 0, "octree coarsening needs even counts >= 2");
+    launch_box_parents(n_fine, parent, child, as_stream(stream));
+  });
+}
+
+mfsem_status mfsem_op_workspace_bytes(const mfsem_op_desc* d, size_t* bytes) {
+  return guarded([&] {
+    require(bytes != nullptr, "bytes is NULL");
+    validate_op(d);
+    mfsem_op op;
+    op_init(op, d);
+    Arena a;
+    op_layout(op, a);
+    *bytes = a.used;
+  });
+}
+
+mfsem_status mfsem_op_create(const mfsem_op_desc* d, void* ws, size_t ws_bytes, void* stream,
+                             mfsem_op** out) {
+  mfsem_op* op = nullptr;
+  mfsem_status st = guarded([&] {
+    require(out != nullptr, "out is NULL");
+    validate_op(d);
+    require(ws != nullptr, "workspace is NULL");
+    require_aligned(ws, 256, "workspace");
+    op = new mfsem_op();
+    op_init(*op, d);
+    Arena a;
+    a.base = static_cast<char*>(ws);
+    a.size = ws_bytes;
+    op_layout(*op, a);
+    hipStream_t s = as_stream(stream);
+    op->tab_host = build_tables(op->d.p, op->d.quad, op->Q, op->d.map_p);
+    op->tab_host32.assign(op->tab_host.begin(), op->tab_host.end());
+    MFSEM_HIP(hipStreamSynchronize(s));
+    MFSEM_HIP(hipMemcpy(op->tab64, op->tab_host.data(), op->tab_host.size() * sizeof(double),
+                        hipMemcpyHostToDevice));
+    MFSEM_HIP(hipMemcpy(op->tab32, op->tab_host32.data(), op->tab_host32.size() * sizeof(float),
+                        hipMemcpyHostToDevice));
+    if (d->sigma)
+      MFSEM_HIP(hipMemcpyAsync(op->sigma_copy, d->sigma,
+                               (size_t)d->batch * d->n_elem * 3 * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+    run_geometry(*op, s);
+    read_bad_flag(*op, s);
+    *out = op;
+  });
+  if (st != MFSEM_OK) delete op;
+  return st;
+}
+
+mfsem_status mfsem_op_destroy(mfsem_op* op) {
+  delete op;
+  return MFSEM_OK;
+}
+
+mfsem_status mfsem_op_set_alpha(mfsem_op* op, double alpha) {
+  return guarded([&] {
+    require(op != nullptr, "operator is NULL");
+    require(alpha >= 0.0 && std::isfinite(alpha), "alpha must be finite and >= 0");
+    op->alpha = alpha;
+    op->d.alpha = alpha;
+  });
+}
+
+mfsem_status mfsem_op_set_sigma(mfsem_op* op, const double* sigma, void* stream) {
+  return guarded([&] {
+    require(op != nullptr && sigma != nullptr, "NULL argument");
+    require(op->sigma_copy != nullptr, "operator was created without per-element sigma");
+    hipStream_t s = as_stream(stream);
+    MFSEM_HIP(hipMemcpyAsync(op->sigma_copy, sigma,
+                             (size_t)op->d.batch * op->d.n_elem * 3 * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    run_geometry(*op, s);
+    read_bad_flag(*op, s);
+  });
+}
+
+mfsem_status mfsem_op_apply(const mfsem_op* op, int32_t dtype, const void* x, void* y,
+                            void* stream) {
+  return guarded([&] {
+    check_op(op, dtype);
+    require(x && y, "x or y is NULL");
+    require(x != y, "x and y must not alias");
+    hipStream_t s = as_stream(stream);
+    if (dtype == MFSEM_F64)
+      launch_apply<double>(*op, static_cast<const double*>(x), static_cast<double*>(y), op->alpha, true, s);
+    else
+      launch_apply<float>(*op, static_cast<const float*>(x), static_cast<float*>(y), op->alpha, true, s);
+  });
+}
+
+mfsem_status mfsem_op_apply_mass(const mfsem_op* op, int32_t dtype, const void* x, void* y,
+                                 void* stream) {
+  return guarded([&] {
+    check_op(op, dtype);
+    require(x && y, "x or y is NULL");
+    require(x != y, "x and y must not alias");
+    hipStream_t s = as_stream(stream);
+    if (dtype == MFSEM_F64)
+      launch_apply<double>(*op, static_cast<const double*>(x), static_cast<double*>(y), 1.0, false, s);
+    else
+      launch_apply<float>(*op, static_cast<const float*>(x), static_cast<float*>(y), 1.0, false, s);
+  });
+}
+
+mfsem_status mfsem_op_diagonal(const mfsem_op* op, int32_t dtype, void* d, void* stream) {
+  return guarded([&] {
+    check_op(op, dtype);
+    require(d != nullptr, "d is NULL");
+    hipStream_t s = as_stream(stream);
+    if (dtype == MFSEM_F64) launch_diag<double>(*op, static_cast<double*>(d), s);
+    else launch_diag<float>(*op, static_cast<float*>(d), s);
+  });
+}
+
+mfsem_status mfsem_op_grad_sigma(const mfsem_op* op, const double* u, const double* w, double* g,
+                                 void* stream) {
+  return guarded([&] {
+    require(op != nullptr, "operator is NULL");
+    require(u && w && g, "NULL argument");
+    launch_grad_sigma(*op, u, w, g, as_stream(stream));
+  });
+}
+
+// -------------------------------------------------------------- multigrid ---
+namespace {
+
+void mg_init(mfsem_mg& mg, const mfsem_mg_desc* d) {
+  require(d != nullptr, "multigrid descriptor is NULL");
+  require(d->n_levels >= 1 && d->n_levels <= 16, "n_levels must be in 1..16");
+  require(d->ops != nullptr, "ops is NULL");
+  require(d->n_levels == 1 || d->transfers != nullptr, "transfers is NULL");
+  require(d->degree >= 1 && d->coarse_degree >= 1, "Chebyshev degrees must be >= 1");
+  require(d->lo_frac > 0.0 && d->hi_frac > d->lo_frac, "need 0 < lo_frac < hi_frac");
+  require(d->eig_iters >= 1 || d->lambda_max, "eig_iters must be >= 1");
+  require(d->precision == MFSEM_F64 || d->precision == MFSEM_F32, "precision must be F64 or F32");
+  mg.d = *d;
+  mg.prec = d->precision;
+  mg.batch = d->ops[0] ? d->ops[0]->d.batch : 1;
+  mg.lv.assign(d->n_levels, mfsem_mg_level{});
+  for (int l = 0; l < d->n_levels; ++l) {
+    const mfsem_op* op = d->ops[l];
+    check_op(op, d->precision);
+    require(op->d.batch == mg.batch, "all levels need the same batch");
+    mfsem_mg_level& L = mg.lv[l];
+    L.op = op;
+    L.n = op->d.n_dof;
+    L.steps = (l + 1 == d->n_levels) ? d->coarse_degree : d->degree;
+    if (l + 1 < d->n_levels) {
+      L.tr = d->transfers[l];
+      const mfsem_op* c = d->ops[l + 1];
+      require(c != nullptr, "NULL level operator");
+      if (L.tr.kind == MFSEM_TRANSFER_P) {
+        require(c->d.n_elem == op->d.n_elem, "p-transfer levels need the same elements");
+        require(c->P <= op->P, "p-transfer must not raise the degree");
+      } else if (L.tr.kind == MFSEM_TRANSFER_H) {
+        require(L.tr.parent && L.tr.child, "h-transfer needs parent and child arrays");
+        require(c->P == op->P, "h-transfer keeps the degree");
+      } else {
+        fail(MFSEM_EINVAL, "unknown transfer kind");
+      }
+    }
+  }
+}
+
+}  // namespace
+
+mfsem_status mfsem_mg_workspace_bytes(const mfsem_mg_desc* d, size_t* bytes) {
+  return guarded([&] {
+    require(bytes != nullptr, "bytes is NULL");
+    mfsem_mg mg;
+    mg_init(mg, d);
+    Arena a;
+    mg_layout(mg, a);
+    *bytes = a.used;
+  });
+}
+
+mfsem_status mfsem_mg_create(const mfsem_mg_desc* d, void* ws, size_t ws_bytes, void* stream,
+                             mfsem_mg** out) {
+  mfsem_mg* mg = nullptr;
+  mfsem_status st = guarded([&] {
+    require(out != nullptr, "out is NULL");
+    require(ws != nullptr, "workspace is NULL");
+    require_aligned(ws, 256, "workspace");
+    mg = new mfsem_mg();
+    mg_init(*mg, d);
+    mg->d.ops = nullptr;        // not kept: the levels hold the pointers
+    mg->d.transfers = nullptr;
+    mg->d.lambda_max = d->lambda_max;
+    Arena a;
+    a.base = static_cast<char*>(ws);
+    a.size = ws_bytes;
+    mg_layout(*mg, a);
+    mg_setup(*mg, as_stream(stream));
+    mg->d.lambda_max = nullptr;
+    *out = mg;
+  });
+  if (st != MFSEM_OK) delete mg;
+  return st;
+}
+
+mfsem_status mfsem_mg_destroy(mfsem_mg* mg) {
+  delete mg;
+  return MFSEM_OK;
+}
+
+mfsem_status mfsem_mg_vcycle(const mfsem_mg* mg, const void* r, void* z, void* stream) {
+  return guarded([&] {
+    require(mg && r && z, "NULL argument");
+    require(r != z, "r and z must not alias");
+    mg_vcycle(*mg, r, z, as_stream(stream));
+  });
+}
+
+mfsem_status mfsem_mg_lambdas(const mfsem_mg* mg, double* lam) {
+  return guarded([&] {
+    require(mg && lam, "NULL argument");
+    for (size_t l = 0; l < mg->lv.size(); ++l)
+      for (int b = 0; b < mg->batch; ++b) lam[l * mg->batch + b] = mg->lv[l].lam[b];
+  });
+}
+
+mfsem_status mfsem_mg_transfer(const mfsem_mg* mg, int32_t level, int32_t direction,
+                               const void* in, void* out, void* stream) {
+  return guarded([&] {
+    require(mg && in && out, "NULL argument");
+    require(in != out, "in and out must not alias");
+    require(level >= 0 && level + 1 < (int)mg->lv.size(), "level out of range");
+    require(direction == 0 || direction == 1, "direction must be 0 or 1");
+    mg_transfer(*mg, level, direction, in, out, as_stream(stream));
+  });
+}
+
+// -------------------------------------------------------------------- PCG ---
+mfsem_status mfsem_pcg_workspace_bytes(const mfsem_op* op, const mfsem_mg* mg, size_t* bytes) {
+  return guarded([&] {
+    require(op && bytes, "NULL argument");
+    *bytes = pcg_bytes(*op, mg);
+  });
+}
+
+mfsem_status mfsem_pcg(const mfsem_op* op, const mfsem_mg* mg, const double* b, double* x,
+                       const mfsem_solve_opts* opts, mfsem_solve_info* info, void* ws,
+                       size_t ws_bytes, void* stream) {
+  mfsem_status solve_status = MFSEM_OK;
+  mfsem_status st = guarded([&] {
+    check_op(op, MFSEM_F64);
+    require(b && x && opts && info && ws, "NULL argument");
+    require(b != x, "b and x must not alias");
+    require_aligned(ws, 256, "workspace");
+    require(opts->max_it >= 1, "max_it must be >= 1");
+    require(opts->rtol >= 0.0 && opts->atol >= 0.0 && (opts->rtol > 0.0 || opts->atol > 0.0),
+            "need rtol > 0 or atol > 0");
+    if (mg) {
+      require(mg->lv[0].op->d.n_dof == op->d.n_dof && mg->batch == op->d.batch,
+              "multigrid finest level does not match the operator");
+    }
+    require(ws_bytes >= pcg_bytes(*op, mg), "workspace too small");
+    solve_status = pcg_solve(*op, mg, b, x, *opts, info, ws, ws_bytes, as_stream(stream));
+    if (solve_status != MFSEM_OK) {
+      std::string m = "PCG did not converge for every batch member (worst status " +
+                      std::to_string((int)solve_status) + ")";
+      set_error(m);
+    }
+  });
+  return st != MFSEM_OK ? st : solve_status;
+}
+
+// ----------------------------------------------------------------- ionic ---
+mfsem_status mfsem_ap_imex_rhs(int64_t n, double dt, double chi, double cm,
+                               const mfsem_ap_params* prm, const double* V, double* w,
+                               const double* i_stim, const double* mass_diag, double* b,
+                               void* stream) {
+  return guarded([&] {
+    require(n >= 0, "n must be >= 0");
+    require(dt > 0.0 && chi > 0.0 && cm > 0.0, "dt, chi and cm must be positive");
+    require(prm != nullptr, "params is NULL");
+    require(prm->v_amp != 0.0 && prm->t_scale > 0.0, "v_amp != 0 and t_scale > 0 required");
+    require(n == 0 || (V && w && mass_diag && b), "NULL array");
+    launch_ap(n, dt, chi, cm, *prm, V, w, i_stim, mass_diag, b, as_stream(stream));
+  });
+}
+
+}  // extern "C"

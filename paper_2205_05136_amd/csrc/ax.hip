@@ -1,0 +1,499 @@
+// Matrix-free application of A = alpha*M + K(sigma) (Section 4: the local
+// action of the operator recomputed cell by cell at each CG iteration, Alg. 1;
+// Section 4.1: sum factorisation of the tensor-product basis).
+//
+// Per element, with the element's DOFs u gathered from the global vector:
+//   reference gradient at each quadrature point by 1D contractions along the
+//   three axes, flux = G * grad (G = W|J| J^{-1} sigma J^{-T}, precomputed),
+//   mass term alpha * W|J| * u, then the transposed 1D contractions, and a
+//   scatter-add of the element result into the global vector.
+//
+// SEM-NI (GLL, quadrature points = nodes): the interpolation is the identity
+// and only the 1D derivative matrix D [P][P] is applied; the mass is diagonal.
+// SEM (Gauss, Q points): values are first interpolated to the Gauss points with
+// B [Q][P] (3 passes), differentiated there with the collocation matrix Dq
+// [Q][Q] (3 passes), and the transposes are applied on the way back.
+//
+// Thread mapping: one lane per (i, j) pencil of the element's face tile, the
+// third axis walked in registers; the first two axes go through LDS.  Several
+// elements share a workgroup so the lanes of a wave64 stay busy.  The global
+// sum is a hardware FP64/FP32 atomic add; y must be zero (or hold what is to be
+// added to) beforehand.
+#include "internal.hpp"
+
+namespace mfsem {
+
+namespace {
+
+constexpr int NT = 256;  // target lanes per workgroup
+
+constexpr int round64(int n) { return ((n + 63) / 64) * 64; }
+
+// ------------------------------------------------------------ SEM-NI ------
+template <int P>
+struct NiCfg {
+  static constexpr int P2 = P * P, P3 = P2 * P;
+  static constexpr int NE = (NT / P2) > 0 ? NT / P2 : 1;
+  static constexpr int THREADS = round64(NE * P2);
+};
+
+template <typename T, int P, bool STIFF>
+__global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
+    int64_t n_elem, int64_t n_dof, const int32_t* __restrict__ ed, const T* __restrict__ G,
+    const T* __restrict__ WJ, T alpha, const T* __restrict__ Dtab, const T* __restrict__ x,
+    T* __restrict__ y) {
+  using C = NiCfg<P>;
+  constexpr int P2 = C::P2, P3 = C::P3, NE = C::NE;
+  __shared__ T sD[P * P];
+  __shared__ T sU[STIFF ? NE * P3 : 1];
+  __shared__ T sV[STIFF ? NE * P3 : 1];
+
+  const int tid = threadIdx.x;
+  const int le = tid / P2, ab = tid % P2;
+  const int ia = ab % P, ib = ab / P;
+  const int64_t e = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NE + le;
+  const bool active = (le < NE) && (e < n_elem);
+  const int bt = blockIdx.y;
+  x += (int64_t)bt * n_dof;
+  y += (int64_t)bt * n_dof;
+
+  if (STIFF)
+    for (int i = tid; i < P * P; i += blockDim.x) sD[i] = Dtab[i];
+
+  T u[P];
+  int gi[P];
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < P; ++c) gi[c] = ed[e * P3 + c * P2 + ab];
+#pragma unroll
+    for (int c = 0; c < P; ++c) u[c] = x[gi[c]];
+  }
+  if (!STIFF) {
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < P; ++c) atomic_add(&y[gi[c]], alpha * WJ[e * P3 + c * P2 + ab] * u[c]);
+    }
+    return;
+  }
+  T* su = sU + le * P3;
+  T* sv = sV + le * P3;
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < P; ++c) su[c * P2 + ab] = u[c];
+  }
+  __syncthreads();
+
+  T ur[P], us[P], ut[P];
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      T r = 0, s = 0, t = 0;
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        r += sD[ia * P + m] * su[c * P2 + ib * P + m];
+        s += sD[ib * P + m] * su[c * P2 + m * P + ia];
+        t += sD[c * P + m] * u[m];
+      }
+      ur[c] = r;
+      us[c] = s;
+      ut[c] = t;
+    }
+  }
+  __syncthreads();
+
+  T ft[P], out[P];
+  if (active) {
+    const T* Ge = G + (int64_t)bt * n_elem * 6 * P3 + e * 6 * P3;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      const int q = c * P2 + ab;
+      const T g00 = Ge[q], g01 = Ge[P3 + q], g02 = Ge[2 * P3 + q];
+      const T g11 = Ge[3 * P3 + q], g12 = Ge[4 * P3 + q], g22 = Ge[5 * P3 + q];
+      su[q] = g00 * ur[c] + g01 * us[c] + g02 * ut[c];
+      sv[q] = g01 * ur[c] + g11 * us[c] + g12 * ut[c];
+      ft[c] = g02 * ur[c] + g12 * us[c] + g22 * ut[c];
+      out[c] = (alpha != T(0)) ? alpha * WJ[e * P3 + q] * u[c] : T(0);
+    }
+  }
+  __syncthreads();
+
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      T v = out[c];
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        v += sD[m * P + ia] * su[c * P2 + ib * P + m];
+        v += sD[m * P + ib] * sv[c * P2 + m * P + ia];
+        v += sD[m * P + c] * ft[m];
+      }
+      atomic_add(&y[gi[c]], v);
+    }
+  }
+}
+
+// --------------------------------------------------------------- SEM -------
+template <int P, int Q>
+struct SemCfg {
+  static constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
+  static constexpr int NE = (NT / Q2) > 0 ? NT / Q2 : 1;
+  static constexpr int THREADS = round64(NE * Q2);
+  static constexpr int L1 = (P3 > P * Q2) ? P3 : P * Q2;   // node values / [c][k2][k1]
+  static constexpr int L2 = (P2 * Q > Q3) ? P2 * Q : Q3;   // [c][b][k1] / flux y
+  static constexpr int L3 = Q3;                            // quad values / flux x
+};
+
+template <typename T, int P, int Q, bool STIFF>
+__global__ __launch_bounds__((SemCfg<P, Q>::THREADS)) void ax_sem_kernel(
+    int64_t n_elem, int64_t n_dof, const int32_t* __restrict__ ed, const T* __restrict__ G,
+    const T* __restrict__ WJ, T alpha, const T* __restrict__ Btab, const T* __restrict__ Dqtab,
+    const T* __restrict__ x, T* __restrict__ y) {
+  using C = SemCfg<P, Q>;
+  constexpr int P2 = C::P2, P3 = C::P3, Q2 = C::Q2, Q3 = C::Q3, NE = C::NE;
+  __shared__ T sB[Q * P];
+  __shared__ T sDq[Q * Q];
+  __shared__ T s1[NE * C::L1];
+  __shared__ T s2[NE * C::L2];
+  __shared__ T s3[NE * C::L3];
+
+  const int tid = threadIdx.x;
+  const int le = tid / Q2, pq = tid % Q2;
+  const int i = pq % Q, j = pq / Q;
+  const int64_t e = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NE + le;
+  const bool active = (le < NE) && (e < n_elem);
+  const bool node = active && i < P && j < P;  // lane owns node pencil (a=i, b=j)
+  const bool rowb = active && j < P;           // lane owns (k1=i, b=j)
+  const int bt = blockIdx.y;
+  x += (int64_t)bt * n_dof;
+  y += (int64_t)bt * n_dof;
+
+  for (int t = tid; t < Q * P; t += blockDim.x) sB[t] = Btab[t];
+  for (int t = tid; t < Q * Q; t += blockDim.x) sDq[t] = Dqtab[t];
+  T* b1 = s1 + le * C::L1;
+  T* b2 = s2 + le * C::L2;
+  T* b3 = s3 + le * C::L3;
+
+  int gi[P];
+  if (node) {
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      gi[c] = ed[e * P3 + c * P2 + j * P + i];
+      b1[c * P2 + j * P + i] = x[gi[c]];
+    }
+  }
+  __syncthreads();
+  // x-interpolation: b2[c][b][k1] = sum_a B[k1][a] u[c][b][a]
+  if (rowb) {
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int a = 0; a < P; ++a) s += sB[i * P + a] * b1[c * P2 + j * P + a];
+      b2[c * P * Q + j * Q + i] = s;
+    }
+  }
+  __syncthreads();
+  // y-interpolation: b1[c][k2][k1] = sum_b B[k2][b] b2[c][b][k1]
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int b = 0; b < P; ++b) s += sB[j * P + b] * b2[c * P * Q + b * Q + i];
+      b1[c * Q2 + j * Q + i] = s;
+    }
+  }
+  __syncthreads();
+  // z-interpolation into registers and b3[k3][k2][k1]
+  T uq[Q];
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < P; ++c) s += sB[k * P + c] * b1[c * Q2 + j * Q + i];
+      uq[k] = s;
+      b3[k * Q2 + j * Q + i] = s;
+    }
+  }
+  __syncthreads();
+
+  T rq[Q];
+  if (STIFF) {
+    T dx[Q], dy[Q], dz[Q];
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        T sx = 0, sy = 0, sz = 0;
+#pragma unroll
+        for (int m = 0; m < Q; ++m) {
+          sx += sDq[i * Q + m] * b3[k * Q2 + j * Q + m];
+          sy += sDq[j * Q + m] * b3[k * Q2 + m * Q + i];
+          sz += sDq[k * Q + m] * uq[m];
+        }
+        dx[k] = sx;
+        dy[k] = sy;
+        dz[k] = sz;
+      }
+    }
+    __syncthreads();
+    T fz[Q];
+    if (active) {
+      const T* Ge = G + (int64_t)bt * n_elem * 6 * Q3 + e * 6 * Q3;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const int q = k * Q2 + j * Q + i;
+        const T g00 = Ge[q], g01 = Ge[Q3 + q], g02 = Ge[2 * Q3 + q];
+        const T g11 = Ge[3 * Q3 + q], g12 = Ge[4 * Q3 + q], g22 = Ge[5 * Q3 + q];
+        b3[q] = g00 * dx[k] + g01 * dy[k] + g02 * dz[k];
+        b2[q] = g01 * dx[k] + g11 * dy[k] + g12 * dz[k];
+        fz[k] = g02 * dx[k] + g12 * dy[k] + g22 * dz[k];
+        rq[k] = (alpha != T(0)) ? alpha * WJ[e * Q3 + q] * uq[k] : T(0);
+      }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        T v = rq[k];
+#pragma unroll
+        for (int m = 0; m < Q; ++m) {
+          v += sDq[m * Q + i] * b3[k * Q2 + j * Q + m];
+          v += sDq[m * Q + j] * b2[k * Q2 + m * Q + i];
+          v += sDq[m * Q + k] * fz[m];
+        }
+        rq[k] = v;
+      }
+    }
+  } else {
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) rq[k] = alpha * WJ[e * Q3 + k * Q2 + j * Q + i] * uq[k];
+    }
+  }
+  // back to the nodes: z-pass from registers into b1[c][k2][k1]
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) s += sB[k * P + c] * rq[k];
+      b1[c * Q2 + j * Q + i] = s;
+    }
+  }
+  __syncthreads();
+  // y-pass: b2[c][b][k1] = sum_k2 B[k2][b] b1[c][k2][k1]
+  if (rowb) {
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) s += sB[k * P + j] * b1[c * Q2 + k * Q + i];
+      b2[c * P * Q + j * Q + i] = s;
+    }
+  }
+  __syncthreads();
+  // x-pass and scatter: v[c][b][a] = sum_k1 B[k1][a] b2[c][b][k1]
+  if (node) {
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) s += sB[k * P + i] * b2[c * P * Q + j * Q + k];
+      atomic_add(&y[gi[c]], s);
+    }
+  }
+}
+
+// --------------------------------------------------------------- fills -----
+template <typename T>
+__global__ void zero_kernel(T* __restrict__ y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) y[i] = T(0);
+}
+
+template <typename T>
+void zero(T* y, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  zero_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(y, n);
+  MFSEM_LAUNCH("zero_kernel");
+}
+
+template <typename T>
+const T* tables_of(const mfsem_op& op);
+template <>
+const double* tables_of<double>(const mfsem_op& op) { return op.tab64; }
+template <>
+const float* tables_of<float>(const mfsem_op& op) { return op.tab32; }
+template <typename T>
+const T* G_of(const mfsem_op& op);
+template <>
+const double* G_of<double>(const mfsem_op& op) { return op.G64; }
+template <>
+const float* G_of<float>(const mfsem_op& op) { return op.G32; }
+template <typename T>
+const T* WJ_of(const mfsem_op& op);
+template <>
+const double* WJ_of<double>(const mfsem_op& op) { return op.WJ64; }
+template <>
+const float* WJ_of<float>(const mfsem_op& op) { return op.WJ32; }
+
+template <typename T, int P, bool STIFF>
+void run_ni(const mfsem_op& op, const T* x, T* y, T alpha, hipStream_t s) {
+  using C = NiCfg<P>;
+  const unsigned nb = blocks_for(op.d.n_elem, C::NE);
+  ax_ni_kernel<T, P, STIFF><<<dim3(nb, op.d.batch), dim3(C::THREADS), 0, s>>>(
+      op.d.n_elem, op.d.n_dof, op.d.elem_dof, G_of<T>(op), WJ_of<T>(op), alpha,
+      tables_of<T>(op) + op.off.Db, x, y);
+  MFSEM_LAUNCH("ax_ni_kernel");
+}
+
+template <typename T, int P, int Q, bool STIFF>
+void run_sem(const mfsem_op& op, const T* x, T* y, T alpha, hipStream_t s) {
+  using C = SemCfg<P, Q>;
+  const unsigned nb = blocks_for(op.d.n_elem, C::NE);
+  const T* tab = tables_of<T>(op);
+  ax_sem_kernel<T, P, Q, STIFF><<<dim3(nb, op.d.batch), dim3(C::THREADS), 0, s>>>(
+      op.d.n_elem, op.d.n_dof, op.d.elem_dof, G_of<T>(op), WJ_of<T>(op), alpha, tab + op.off.B,
+      tab + op.off.Dq, x, y);
+  MFSEM_LAUNCH("ax_sem_kernel");
+}
+
+template <typename T, bool STIFF>
+void dispatch(const mfsem_op& op, const T* x, T* y, T alpha, hipStream_t s) {
+  const int P = op.P, Q = op.Q;
+  if (op.d.quad == MFSEM_GLL) {
+    switch (P) {
+      case 2: return run_ni<T, 2, STIFF>(op, x, y, alpha, s);
+      case 3: return run_ni<T, 3, STIFF>(op, x, y, alpha, s);
+      case 4: return run_ni<T, 4, STIFF>(op, x, y, alpha, s);
+      case 5: return run_ni<T, 5, STIFF>(op, x, y, alpha, s);
+      case 6: return run_ni<T, 6, STIFF>(op, x, y, alpha, s);
+      case 7: return run_ni<T, 7, STIFF>(op, x, y, alpha, s);
+      case 8: return run_ni<T, 8, STIFF>(op, x, y, alpha, s);
+      case 9: return run_ni<T, 9, STIFF>(op, x, y, alpha, s);
+    }
+  } else {
+#define MFSEM_SEM_CASE(PP)                                               \
+  case PP:                                                               \
+    if (Q == PP) return run_sem<T, PP, PP, STIFF>(op, x, y, alpha, s);   \
+    if (Q == PP + 1) return run_sem<T, PP, PP + 1, STIFF>(op, x, y, alpha, s); \
+    if (Q == PP + 2) return run_sem<T, PP, PP + 2, STIFF>(op, x, y, alpha, s); \
+    break;
+    switch (P) {
+      MFSEM_SEM_CASE(2)
+      MFSEM_SEM_CASE(3)
+      MFSEM_SEM_CASE(4)
+      MFSEM_SEM_CASE(5)
+      MFSEM_SEM_CASE(6)
+      MFSEM_SEM_CASE(7)
+      MFSEM_SEM_CASE(8)
+      MFSEM_SEM_CASE(9)
+    }
+#undef MFSEM_SEM_CASE
+  }
+  fail(MFSEM_EUNSUPPORTED, "no apply kernel for this (p, quadrature) pair");
+}
+
+// ------------------------------------------------------------ diagonal -----
+// diag(A)_i = sum_e sum_k [alpha W|J| phi_i^2 + grad_ref(phi_i)^T G grad_ref(phi_i)],
+// with phi_i = l_a l_b l_c and grad_ref = (l_a' l_b l_c, l_a l_b' l_c, l_a l_b l_c').
+// One workgroup per element; each of the 7 stored fields is staged in LDS in
+// turn and every lane accumulates its nodes' sums over all quadrature points.
+constexpr int DIAG_THREADS = 256;
+constexpr int MAXQ = MFSEM_MAX_P + 3, MAXP = MFSEM_MAX_P + 1;
+
+template <typename T>
+__global__ __launch_bounds__(DIAG_THREADS) void diag_kernel(
+    int64_t n_elem, int64_t n_dof, int P, int Q, const int32_t* __restrict__ ed,
+    const T* __restrict__ G, const T* __restrict__ WJ, T alpha, const T* __restrict__ Btab,
+    const T* __restrict__ Dbtab, T* __restrict__ d) {
+  __shared__ T sB[MAXQ * MAXP], sD[MAXQ * MAXP];
+  __shared__ T sF[MAXQ * MAXQ * MAXQ];
+  const int64_t e = blockIdx.x;
+  const int bt = blockIdx.y;
+  const int P3 = P * P * P, Q3 = Q * Q * Q;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < Q * P; t += blockDim.x) {
+    sB[t] = Btab[t];
+    sD[t] = Dbtab[t];
+  }
+  constexpr int MAXN = (MAXP * MAXP * MAXP + DIAG_THREADS - 1) / DIAG_THREADS;
+  T acc[MAXN];
+  for (int r = 0; r < MAXN; ++r) acc[r] = 0;
+  const T* Ge = G + ((int64_t)bt * n_elem + e) * 6 * Q3;
+  // field f: 0 = alpha*WJ, 1 = G00, 2 = G11, 3 = G22, 4 = G01, 5 = G02, 6 = G12
+  const int gidx[7] = {-1, 0, 3, 5, 1, 2, 4};
+  for (int f = 0; f < 7; ++f) {
+    __syncthreads();
+    for (int k = tid; k < Q3; k += blockDim.x)
+      sF[k] = (f == 0) ? alpha * WJ[e * Q3 + k] : Ge[(int64_t)gidx[f] * Q3 + k];
+    __syncthreads();
+    for (int r = 0; r < MAXN; ++r) {
+      const int l = tid + r * DIAG_THREADS;
+      if (l >= P3) break;
+      const int a = l % P, b = (l / P) % P, c = l / (P * P);
+      T s = 0;
+      for (int k3 = 0; k3 < Q; ++k3) {
+        const T Bz = sB[k3 * P + c], Dz = sD[k3 * P + c];
+        for (int k2 = 0; k2 < Q; ++k2) {
+          const T By = sB[k2 * P + b], Dy = sD[k2 * P + b];
+          for (int k1 = 0; k1 < Q; ++k1) {
+            const T Bx = sB[k1 * P + a], Dx = sD[k1 * P + a];
+            T w;
+            switch (f) {
+              case 0: w = Bx * By * Bz; w = w * w; break;
+              case 1: w = Dx * By * Bz; w = w * w; break;
+              case 2: w = Bx * Dy * Bz; w = w * w; break;
+              case 3: w = Bx * By * Dz; w = w * w; break;
+              case 4: w = T(2) * (Dx * By * Bz) * (Bx * Dy * Bz); break;
+              case 5: w = T(2) * (Dx * By * Bz) * (Bx * By * Dz); break;
+              default: w = T(2) * (Bx * Dy * Bz) * (Bx * By * Dz); break;
+            }
+            s += w * sF[k3 * Q * Q + k2 * Q + k1];
+          }
+        }
+      }
+      acc[r] += s;
+    }
+  }
+  for (int r = 0; r < MAXN; ++r) {
+    const int l = tid + r * DIAG_THREADS;
+    if (l >= P3) break;
+    atomic_add(&d[(int64_t)bt * n_dof + ed[e * P3 + l]], acc[r]);
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_apply(const mfsem_op& op, const T* x, T* y, double alpha, bool stiffness,
+                  hipStream_t s) {
+  zero<T>(y, op.d.n_dof * op.d.batch, s);
+  if (op.d.n_elem == 0) return;
+  if (stiffness) dispatch<T, true>(op, x, y, (T)alpha, s);
+  else dispatch<T, false>(op, x, y, (T)alpha, s);
+}
+
+template <typename T>
+void launch_diag(const mfsem_op& op, T* d, hipStream_t s) {
+  zero<T>(d, op.d.n_dof * op.d.batch, s);
+  if (op.d.n_elem == 0) return;
+  const T* tab = tables_of<T>(op);
+  diag_kernel<T><<<dim3((unsigned)op.d.n_elem, op.d.batch), dim3(DIAG_THREADS), 0, s>>>(
+      op.d.n_elem, op.d.n_dof, op.P, op.Q, op.d.elem_dof, G_of<T>(op), WJ_of<T>(op),
+      (T)op.alpha, tab + op.off.B, tab + op.off.Db, d);
+  MFSEM_LAUNCH("diag_kernel");
+}
+
+template void launch_apply<double>(const mfsem_op&, const double*, double*, double, bool,
+                                   hipStream_t);
+template void launch_apply<float>(const mfsem_op&, const float*, float*, double, bool,
+                                  hipStream_t);
+template void launch_diag<double>(const mfsem_op&, double*, hipStream_t);
+template void launch_diag<float>(const mfsem_op&, float*, hipStream_t);
+
+}  // namespace mfsem

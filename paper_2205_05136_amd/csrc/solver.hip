@@ -1,0 +1,454 @@
+// Geometric multigrid V-cycle with Chebyshev-Jacobi smoothing, and the (P)CG
+// driver (Sections 4 and 4.3; smoother parameters from Section 5).
+//
+// Chebyshev smoothing of A x = b on [lo, hi] * lambda_max, with
+// theta = (l_hi + l_lo)/2, delta = (l_hi - l_lo)/2, s = theta/delta, rho_1 = 1/s:
+//   step 1:  d = D^{-1} (b - A x0) / theta,            x = x0 + d
+//   step j:  rho_j = 1/(2s - rho_{j-1}),
+//            d = rho_j rho_{j-1} d + (2 rho_j/delta) D^{-1}(b - A x),  x += d
+// From x0 = 0 the first product with A is skipped.  lambda_max per level
+// comes from the Lanczos tridiagonal of a few Jacobi-preconditioned CG steps.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "solver.hpp"
+
+namespace mfsem {
+
+namespace {
+
+template <typename T>
+T* P_(void* p) { return static_cast<T*>(p); }
+
+// Largest eigenvalue of a symmetric tridiagonal matrix by Sturm-sequence bisection.
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int m = (int)a.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {  // number of eigenvalues < x
+    int c = 0;
+    double q = a[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < m; ++i) {
+      const double qq = (q == 0.0) ? 1e-300 : q;
+      q = a[i] - x - b[i - 1] * b[i - 1] / qq;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= m) hi = mid;  // all eigenvalues below mid
+    else lo = mid;
+  }
+  return hi;
+}
+
+template <typename T>
+void estimate_lambda(mfsem_mg& mg, mfsem_mg_level& L, int level, double* scratch_c,
+                     hipStream_t s) {
+  const int B = mg.batch;
+  const int64_t n = L.n;
+  // vectors: b, x, t, d of the level serve as r, z, q, p; a double buffer for v0
+  T* r = P_<T>(L.b);
+  T* z = P_<T>(L.x);
+  T* q = P_<T>(L.t);
+  T* p = P_<T>(L.d);
+  const T* dinv = P_<T>(L.dinv);
+  // seeded start vector (splitmix64 counter generator); for FP32 it is drawn
+  // in FP64 into the level's x buffer (sized for doubles) and rounded
+  const uint64_t seed = mg.d.eig_seed + 0x1000193ull * (uint64_t)level;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    vrandom(reinterpret_cast<double*>(r), n * B, seed, s);
+  } else {
+    double* tmp = reinterpret_cast<double*>(z);
+    vrandom(tmp, n * B, seed, s);
+    vcast<double, float>(tmp, reinterpret_cast<float*>(r), n * B, s);
+  }
+  double* red = scratch_c;                 // [B][2]
+  double* partial = scratch_c + 2 * B;     // [B][nblk][2]
+  double* cdev = partial + 2 * (size_t)dot_blocks(n) * B;  // [B][2]
+  std::vector<double> hc(2 * B), hred(2 * B), rz(B), alpha(B), beta(B);
+  std::vector<std::vector<double>> al(B), be(B);
+  vmul<T>(z, dinv, r, n, B, s);
+  for (int b = 0; b < B; ++b) { hc[2 * b] = 0.0; hc[2 * b + 1] = 1.0; }
+  MFSEM_HIP(hipMemcpy(cdev, hc.data(), 2 * B * sizeof(double), hipMemcpyHostToDevice));
+  vlin<T>(p, z, n, B, cdev, s);
+  vdot2<T>(r, z, nullptr, n, B, partial, red, s);
+  MFSEM_HIP(hipMemcpyAsync(hred.data(), red, 2 * B * sizeof(double), hipMemcpyDeviceToHost, s));
+  MFSEM_HIP(hipStreamSynchronize(s));
+  for (int b = 0; b < B; ++b) rz[b] = hred[2 * b];
+  std::vector<int> live(B, 1);
+  for (int it = 0; it < mg.d.eig_iters; ++it) {
+    launch_apply<T>(*L.op, p, q, L.op->alpha, true, s);
+    vdot2<T>(p, q, nullptr, n, B, partial, red, s);
+    MFSEM_HIP(hipMemcpyAsync(hred.data(), red, 2 * B * sizeof(double), hipMemcpyDeviceToHost, s));
+    MFSEM_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < B; ++b) {
+      const double pq = hred[2 * b];
+      if (!(pq > 0.0) || !(rz[b] > 0.0)) live[b] = 0;
+      alpha[b] = live[b] ? rz[b] / pq : 0.0;
+      hc[2 * b] = 1.0;
+      hc[2 * b + 1] = -alpha[b];
+    }
+    MFSEM_HIP(hipMemcpy(cdev, hc.data(), 2 * B * sizeof(double), hipMemcpyHostToDevice));
+    vlin<T>(r, q, n, B, cdev, s);
+    vmul<T>(z, dinv, r, n, B, s);
+    vdot2<T>(r, z, nullptr, n, B, partial, red, s);
+    MFSEM_HIP(hipMemcpyAsync(hred.data(), red, 2 * B * sizeof(double), hipMemcpyDeviceToHost, s));
+    MFSEM_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < B; ++b) {
+      if (live[b]) {
+        const double rzn = hred[2 * b];
+        beta[b] = rzn / rz[b];
+        al[b].push_back(alpha[b]);
+        be[b].push_back(beta[b]);
+        rz[b] = rzn;
+        if (!(rzn > 0.0)) live[b] = 0;
+      } else {
+        beta[b] = 0.0;
+      }
+      hc[2 * b] = beta[b];
+      hc[2 * b + 1] = 1.0;
+    }
+    MFSEM_HIP(hipMemcpy(cdev, hc.data(), 2 * B * sizeof(double), hipMemcpyHostToDevice));
+    vlin<T>(p, z, n, B, cdev, s);
+  }
+  L.lam.assign(B, 0.0);
+  for (int b = 0; b < B; ++b) {
+    const int m = (int)al[b].size();
+    if (m == 0) fail(MFSEM_EBREAKDOWN, "eigenvalue estimate: CG broke down at the first step");
+    std::vector<double> da(m), off(m > 1 ? m - 1 : 0);
+    for (int j = 0; j < m; ++j) {
+      da[j] = 1.0 / al[b][j] + (j > 0 ? be[b][j - 1] / al[b][j - 1] : 0.0);
+      if (j + 1 < m) off[j] = std::sqrt(be[b][j]) / al[b][j];
+    }
+    L.lam[b] = tridiag_max_eig(da, off);
+  }
+}
+
+void cheb_coefficients(const mfsem_mg& mg, const mfsem_mg_level& L, std::vector<double>& out) {
+  const int B = mg.batch;
+  out.assign((size_t)L.steps * B * 2, 0.0);
+  for (int b = 0; b < B; ++b) {
+    const double lmax = L.lam[b];
+    const double lo = mg.d.lo_frac * lmax, hi = mg.d.hi_frac * lmax;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+    const double sig = theta / delta;
+    double rho = 1.0 / sig;
+    for (int j = 0; j < L.steps; ++j) {
+      double c1, c2;
+      if (j == 0) {
+        c1 = 0.0;
+        c2 = 1.0 / theta;
+      } else {
+        const double rn = 1.0 / (2.0 * sig - rho);
+        c1 = rn * rho;
+        c2 = 2.0 * rn / delta;
+        rho = rn;
+      }
+      out[((size_t)j * B + b) * 2] = c1;
+      out[((size_t)j * B + b) * 2 + 1] = c2;
+    }
+  }
+}
+
+template <typename T>
+TransferArgs<T> transfer_args(const mfsem_mg& mg, int l) {
+  const mfsem_mg_level& F = mg.lv[l];
+  const mfsem_mg_level& C = mg.lv[l + 1];
+  TransferArgs<T> a;
+  a.n_elem_f = F.op->d.n_elem;
+  a.Pf = F.op->P;
+  a.Pc = C.op->P;
+  a.ed_f = F.op->d.elem_dof;
+  a.ed_c = C.op->d.elem_dof;
+  a.parent = F.tr.kind == MFSEM_TRANSFER_H ? F.tr.parent : nullptr;
+  a.child = F.tr.kind == MFSEM_TRANSFER_H ? F.tr.child : nullptr;
+  a.I = P_<T>(F.I);
+  a.nf = F.n;
+  a.nc = C.n;
+  return a;
+}
+
+template <typename T>
+void smooth(const mfsem_mg& mg, const mfsem_mg_level& L, const T* b, T* x, bool from_zero,
+            hipStream_t s) {
+  const int B = mg.batch;
+  T* t = P_<T>(L.t);
+  T* d = P_<T>(L.d);
+  const T* dinv = P_<T>(L.dinv);
+  for (int j = 0; j < L.steps; ++j) {
+    const double* c = L.coef + (size_t)j * B * 2;
+    if (j == 0 && from_zero) {
+      vcheb<T>(x, d, b, nullptr, dinv, L.n, B, c, true, s);
+    } else {
+      launch_apply<T>(*L.op, x, t, L.op->alpha, true, s);
+      vcheb<T>(x, d, b, t, dinv, L.n, B, c, false, s);
+    }
+  }
+}
+
+template <typename T>
+void vcycle(const mfsem_mg& mg, int l, const T* b, T* x, hipStream_t s) {
+  const mfsem_mg_level& L = mg.lv[l];
+  const int B = mg.batch;
+  if (l + 1 == (int)mg.lv.size()) {
+    smooth<T>(mg, L, b, x, true, s);
+    return;
+  }
+  const mfsem_mg_level& C = mg.lv[l + 1];
+  smooth<T>(mg, L, b, x, true, s);
+  T* t = P_<T>(L.t);
+  launch_apply<T>(*L.op, x, t, L.op->alpha, true, s);
+  const TransferArgs<T> ta = transfer_args<T>(mg, l);
+  vfill<T>(P_<T>(C.b), C.n * B, T(0), s);
+  launch_restrict<T>(ta, B, b, t, P_<T>(L.wmult), P_<T>(C.b), s);
+  vcycle<T>(mg, l + 1, P_<T>(C.b), P_<T>(C.x), s);
+  launch_prolong<T>(ta, B, P_<T>(C.x), t, s);
+  vaxpy<T>(x, t, L.n * B, s);
+  smooth<T>(mg, L, b, x, false, s);
+}
+
+}  // namespace
+
+void mg_layout(mfsem_mg& mg, Arena& a) {
+  const size_t w = mg.prec == MFSEM_F64 ? sizeof(double) : sizeof(float);
+  const int B = mg.batch;
+  size_t scratch = 0;
+  for (size_t l = 0; l < mg.lv.size(); ++l) {
+    mfsem_mg_level& L = mg.lv[l];
+    const size_t nb = (size_t)L.n * B;
+    L.dinv = a.take(nb * w);
+    L.t = a.take(nb * w);
+    L.d = a.take(nb * w);
+    // level 0 keeps its own b/x too: the eigenvalue estimate works in them
+    L.b = a.take(nb * w);
+    L.x = a.take(nb * std::max(w, sizeof(double)));
+    L.coef = a.take_n<double>((size_t)std::max(1, L.steps) * B * 2);
+    if (l + 1 < mg.lv.size()) {
+      L.wmult = a.take(L.n * w);
+      const int Pf = L.op->P, Pc = mg.lv[l + 1].op->P;
+      L.I = a.take((size_t)2 * Pf * Pc * w);
+    }
+    scratch = std::max(scratch, (size_t)(4 * B + 2 * (size_t)dot_blocks(L.n) * B));
+  }
+  mg.scratch = a.take_n<double>(scratch);
+}
+
+void mg_setup(mfsem_mg& mg, hipStream_t s) {
+  const int B = mg.batch;
+  const bool f64 = mg.prec == MFSEM_F64;
+  for (size_t l = 0; l < mg.lv.size(); ++l) {
+    mfsem_mg_level& L = mg.lv[l];
+    if (f64) {
+      launch_diag<double>(*L.op, P_<double>(L.dinv), s);
+      vinvert<double>(P_<double>(L.dinv), L.n * B, s);
+    } else {
+      launch_diag<float>(*L.op, P_<float>(L.dinv), s);
+      vinvert<float>(P_<float>(L.dinv), L.n * B, s);
+    }
+    if (l + 1 < mg.lv.size()) {
+      const mfsem_op& F = *L.op;
+      const int P3 = F.P * F.P * F.P;
+      if (f64) launch_inv_multiplicity<double>(F.d.elem_dof, F.d.n_elem, P3, L.n, P_<double>(L.wmult), s);
+      else launch_inv_multiplicity<float>(F.d.elem_dof, F.d.n_elem, P3, L.n, P_<float>(L.wmult), s);
+      std::vector<double> I = transfer_matrices(L.tr.kind, F.P - 1, mg.lv[l + 1].op->P - 1);
+      MFSEM_HIP(hipStreamSynchronize(s));
+      if (f64) {
+        MFSEM_HIP(hipMemcpy(L.I, I.data(), I.size() * sizeof(double), hipMemcpyHostToDevice));
+      } else {
+        std::vector<float> If(I.begin(), I.end());
+        MFSEM_HIP(hipMemcpy(L.I, If.data(), If.size() * sizeof(float), hipMemcpyHostToDevice));
+      }
+    }
+  }
+  MFSEM_HIP(hipStreamSynchronize(s));
+  for (size_t l = 0; l < mg.lv.size(); ++l) {
+    mfsem_mg_level& L = mg.lv[l];
+    if (mg.d.lambda_max) {
+      L.lam.assign(mg.d.lambda_max + l * B, mg.d.lambda_max + (l + 1) * B);
+    } else if (f64) {
+      estimate_lambda<double>(mg, L, (int)l, mg.scratch, s);
+    } else {
+      estimate_lambda<float>(mg, L, (int)l, mg.scratch, s);
+    }
+    for (int b = 0; b < B; ++b)
+      if (!(L.lam[b] > 0.0) || !std::isfinite(L.lam[b]))
+        fail(MFSEM_EBREAKDOWN, "non-positive lambda_max on multigrid level " + std::to_string(l));
+    std::vector<double> c;
+    cheb_coefficients(mg, L, c);
+    MFSEM_HIP(hipMemcpy(L.coef, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+}
+
+template <typename T>
+void transfer_t(const mfsem_mg& mg, int l, int direction, const T* in, T* out, hipStream_t s) {
+  const TransferArgs<T> ta = transfer_args<T>(mg, l);
+  if (direction == 0) {
+    launch_prolong<T>(ta, mg.batch, in, out, s);
+  } else {
+    vfill<T>(out, mg.lv[l + 1].n * mg.batch, T(0), s);
+    launch_restrict<T>(ta, mg.batch, in, nullptr, P_<T>(mg.lv[l].wmult), out, s);
+  }
+}
+
+void mg_transfer(const mfsem_mg& mg, int level, int direction, const void* in, void* out,
+                 hipStream_t s) {
+  if (mg.prec == MFSEM_F64)
+    transfer_t<double>(mg, level, direction, static_cast<const double*>(in), static_cast<double*>(out), s);
+  else
+    transfer_t<float>(mg, level, direction, static_cast<const float*>(in), static_cast<float*>(out), s);
+}
+
+void mg_vcycle(const mfsem_mg& mg, const void* r, void* z, hipStream_t s) {
+  if (mg.prec == MFSEM_F64) vcycle<double>(mg, 0, static_cast<const double*>(r), static_cast<double*>(z), s);
+  else vcycle<float>(mg, 0, static_cast<const float*>(r), static_cast<float*>(z), s);
+}
+
+// ------------------------------------------------------------------ PCG ---
+namespace {
+
+struct PcgWs {
+  double *r, *z, *p, *q, *zo;
+  float *r32, *z32;
+  PcgScalars* sc;
+  double *partial, *red;
+};
+
+PcgWs pcg_layout(const mfsem_op& op, const mfsem_mg* mg, bool flexible, Arena& a) {
+  const size_t nb = (size_t)op.d.n_dof * op.d.batch;
+  PcgWs w{};
+  w.r = a.take_n<double>(nb);
+  w.z = a.take_n<double>(nb);
+  w.p = a.take_n<double>(nb);
+  w.q = a.take_n<double>(nb);
+  w.zo = a.take_n<double>(nb);  // used by the flexible variant
+  (void)flexible;
+  if (mg && mg->prec == MFSEM_F32) {
+    w.r32 = a.take_n<float>(nb);
+    w.z32 = a.take_n<float>(nb);
+  }
+  w.sc = a.take_n<PcgScalars>(op.d.batch);
+  w.partial = a.take_n<double>(2 * (size_t)dot_blocks(op.d.n_dof) * op.d.batch);
+  w.red = a.take_n<double>(2 * (size_t)op.d.batch);
+  return w;
+}
+
+}  // namespace
+
+size_t pcg_bytes(const mfsem_op& op, const mfsem_mg* mg) {
+  Arena a;
+  pcg_layout(op, mg, true, a);
+  return a.used;
+}
+
+mfsem_status pcg_solve(const mfsem_op& op, const mfsem_mg* mg, const double* b, double* x,
+                       const mfsem_solve_opts& o, mfsem_solve_info* info, void* ws,
+                       size_t ws_bytes, hipStream_t s) {
+  Arena a;
+  a.base = static_cast<char*>(ws);
+  a.size = ws_bytes;
+  const PcgWs w = pcg_layout(op, mg, o.flexible != 0, a);
+  const int B = op.d.batch;
+  const int64_t n = op.d.n_dof;
+  const size_t nb = (size_t)n * B;
+  std::vector<PcgScalars> hs(B);
+  for (int i = 0; i < B; ++i) {
+    hs[i] = PcgScalars{};
+    hs[i].active = 1;
+    hs[i].flexible = o.flexible ? 1 : 0;
+  }
+  MFSEM_HIP(hipStreamSynchronize(s));
+  MFSEM_HIP(hipMemcpy(w.sc, hs.data(), B * sizeof(PcgScalars), hipMemcpyHostToDevice));
+
+  auto precondition = [&]() {
+    if (!mg) {
+      MFSEM_HIP(hipMemcpyAsync(w.z, w.r, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else if (mg->prec == MFSEM_F64) {
+      mg_vcycle(*mg, w.r, w.z, s);
+    } else {
+      vcast<double, float>(w.r, w.r32, (int64_t)nb, s);
+      mg_vcycle(*mg, w.r32, w.z32, s);
+      vcast<float, double>(w.z32, w.z, (int64_t)nb, s);
+    }
+  };
+  auto fetch = [&]() {
+    MFSEM_HIP(hipMemcpyAsync(hs.data(), w.sc, B * sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+    MFSEM_HIP(hipStreamSynchronize(s));
+  };
+
+  // r = b - A x
+  launch_apply<double>(op, x, w.q, op.alpha, true, s);
+  vresidual(b, w.q, w.r, n, B, w.partial, w.red, s);
+  pcg_scalars(w.sc, w.red, B, PCG_SET_RR_BB, s);
+  fetch();
+  std::vector<double> tol(B);
+  std::vector<char> done(B, 0);
+  bool changed = false;
+  int live = 0;
+  for (int i = 0; i < B; ++i) {
+    info[i] = mfsem_solve_info{};
+    info[i].b_norm = std::sqrt(hs[i].bb);
+    info[i].r0_norm = std::sqrt(hs[i].rr);
+    info[i].r_norm = info[i].r0_norm;
+    tol[i] = std::max(o.rtol * info[i].b_norm, o.atol);
+    if (!std::isfinite(hs[i].rr)) info[i].status = MFSEM_ENONFINITE;
+    if (info[i].status != MFSEM_OK || info[i].r0_norm <= tol[i]) {
+      hs[i].active = 0;
+      done[i] = 1;
+      changed = true;
+    }
+    live += !done[i];
+  }
+  if (changed) MFSEM_HIP(hipMemcpy(w.sc, hs.data(), B * sizeof(PcgScalars), hipMemcpyHostToDevice));
+
+  for (int it = 1; live > 0 && it <= o.max_it; ++it) {
+    precondition();
+    vdot2<double>(w.r, w.z, o.flexible ? w.zo : nullptr, n, B, w.partial, w.red, s);
+    pcg_scalars(w.sc, w.red, B, it == 1 ? PCG_SET_RZ_FIRST : PCG_SET_RZ, s);
+    if (o.flexible)
+      MFSEM_HIP(hipMemcpyAsync(w.zo, w.z, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+    vp(w.p, w.z, n, B, w.sc, s);
+    launch_apply<double>(op, w.p, w.q, op.alpha, true, s);
+    vdot2<double>(w.p, w.q, nullptr, n, B, w.partial, w.red, s);
+    pcg_scalars(w.sc, w.red, B, PCG_SET_PQ, s);
+    vxr(x, w.r, w.p, w.q, n, B, w.sc, w.partial, w.red, s);
+    pcg_scalars(w.sc, w.red, B, PCG_SET_RR, s);
+    fetch();
+    changed = false;
+    live = 0;
+    for (int i = 0; i < B; ++i) {
+      if (done[i]) continue;
+      info[i].iters = it;
+      if (hs[i].flag != 0) {  // breakdown or non-finite found on the device
+        info[i].status = hs[i].flag;
+        done[i] = 1;
+        continue;
+      }
+      info[i].r_norm = std::sqrt(hs[i].rr);
+      if (!std::isfinite(hs[i].rr)) info[i].status = MFSEM_ENONFINITE;
+      if (info[i].status != MFSEM_OK || info[i].r_norm <= tol[i]) {
+        hs[i].active = 0;
+        done[i] = 1;
+        changed = true;
+      }
+      live += !done[i];
+    }
+    if (changed) MFSEM_HIP(hipMemcpy(w.sc, hs.data(), B * sizeof(PcgScalars), hipMemcpyHostToDevice));
+  }
+  mfsem_status worst = MFSEM_OK;
+  for (int i = 0; i < B; ++i) {
+    if (info[i].status == MFSEM_OK && info[i].r_norm > tol[i]) info[i].status = MFSEM_ENOCONV;
+    if (info[i].status != MFSEM_OK && (worst == MFSEM_OK || info[i].status < worst))
+      worst = (mfsem_status)info[i].status;
+  }
+  return worst;
+}
+
+}  // namespace mfsem

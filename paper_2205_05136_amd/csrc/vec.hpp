@@ -1,0 +1,47 @@
+// Vector kernels used by the Krylov and multigrid drivers.
+#pragma once
+
+#include "internal.hpp"
+
+namespace mfsem {
+
+// Per-member (P)CG scalars, kept in device memory.
+struct PcgScalars {
+  double rz, pq, rr, bb, alpha, beta;
+  int32_t active, flag, flexible, pad;
+};
+
+enum { PCG_SET_RR_BB = 0, PCG_SET_PQ = 1, PCG_SET_RR = 2, PCG_SET_RZ_FIRST = 3, PCG_SET_RZ = 4 };
+
+int dot_blocks(int64_t n);  // partial-sum blocks per member for vectors of length n
+
+// out[bt*2 + {0,1}] = (a.b, a.c) per member (c may be null -> 0)
+template <typename T>
+void vdot2(const T* a, const T* b, const T* c, int64_t n, int batch, double* partial,
+           double* out, hipStream_t s);
+// r = b - q (q may be null), out = (r.r, b.b)
+void vresidual(const double* b, const double* q, double* r, int64_t n, int batch,
+               double* partial, double* out, hipStream_t s);
+// x += alpha p, r -= alpha q with alpha from sc; out[bt*2] = r.r
+void vxr(double* x, double* r, const double* p, const double* q, int64_t n, int batch,
+         const PcgScalars* sc, double* partial, double* out, hipStream_t s);
+// p = z + beta p (p = z when beta == 0)
+void vp(double* p, const double* z, int64_t n, int batch, const PcgScalars* sc, hipStream_t s);
+void pcg_scalars(PcgScalars* sc, const double* red, int batch, int what, hipStream_t s);
+// d = c1 d + c2 dinv (b - t); x = overwrite ? d : x + d   (coef [batch][2])
+template <typename T>
+void vcheb(T* x, T* d, const T* b, const T* t, const T* dinv, int64_t n, int batch,
+           const double* coef, bool overwrite, hipStream_t s);
+template <typename T>
+void vaxpy(T* y, const T* x, int64_t n, hipStream_t s);
+template <typename T>
+void vinvert(T* x, int64_t n, hipStream_t s);
+void vrandom(double* x, int64_t n, uint64_t seed, hipStream_t s);
+// y = c[bt][0] y + c[bt][1] x   (c [batch][2] in device memory; y ignored when c0 == 0)
+template <typename T>
+void vlin(T* y, const T* x, int64_t n, int batch, const double* c, hipStream_t s);
+// z = w o r
+template <typename T>
+void vmul(T* z, const T* w, const T* r, int64_t n, int batch, hipStream_t s);
+
+}  // namespace mfsem

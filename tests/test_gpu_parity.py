@@ -1,0 +1,329 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Bars: FP64 relative L2 <= 1e-12 (apply, mass, diagonal, transfers, V-cycle,
+solve, gradient); integer outputs bit-exact; FP32 applies <= 1e-5 (rounding of
+G and vectors to single precision: ~P^4 terms of size 1 summed per output,
+each with relative error 6e-8); mixed-precision solves <= 1e-8 against the
+FP64 solution."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import synth
+from gpu_common import announce, jitter_scale, oracle_problem, rel_l2, to_dev, to_np
+from oracle import adjoint as oadj
+from oracle import ionic as oion
+from oracle import mesh as omesh
+from oracle import multigrid as omg
+from oracle import operator as oop
+from oracle import solvers as osol
+
+pytestmark = pytest.mark.gpu
+
+mf = pytest.importorskip("paper_2205_05136_amd")
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+# Meshes that span several workgroups and leave a ragged last one (p <= 5:
+# 63 elements; p >= 6: 10 elements, which the oracle still assembles in seconds).
+RAG = (7, 3, 3)
+RAG_HI = (5, 2, 1)
+
+
+def _spec(p, n=None, **kw):
+    n = n or (RAG if p <= 5 else RAG_HI)
+    return synth.slab(p, n).with_(**kw)
+
+
+def _op(spec, jitter=None, sigma=None, **kw):
+    box = mf.Box.from_spec(spec)
+    xyz = None
+    if jitter is not None:
+        xyz = box.xyz + to_dev(synth.node_jitter(jitter[0], spec.n_dof, jitter[1]))
+    return mf.Operator.from_spec(spec, box=box, xyz=xyz, sigma=sigma, **kw), box
+
+
+# ------------------------------------------------------------------ meshes ---
+@pytest.mark.parametrize("spec", [synth.C1, _spec(4), _spec(7, (3, 2, 2)), synth.C2],
+                         ids=["c1", "slab-p4", "slab-p7", "c2"])
+def test_box_matches_oracle(spec):
+    announce(f"box {spec.p} {spec.n}")
+    box = mf.Box.from_spec(spec)
+    m = omesh.box(spec)
+    assert np.array_equal(box.elem_dof.cpu().numpy().astype(np.int64), m.elem_dof)
+    np.testing.assert_allclose(to_np(box.xyz), m.xyz, rtol=0, atol=1e-13 * max(spec.length))
+    if spec.fiber:
+        np.testing.assert_allclose(to_np(box.fiber), m.fiber, rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------------------- apply ---
+APPLY_CASES = (
+    [("c1", synth.C1, None, None)]
+    + [(f"gll-p{p}", _spec(p), None, None) for p in range(1, 9)]
+    + [("gll-p3-jitter", _spec(3), (17, None), None),
+       ("gll-p5-sigma", _spec(5), None, 3),
+       ("gll-p2-iso-jitter", synth.BoxSpec(p=2, n=(5, 4, 3), length=(1.0, 0.8, 0.6),
+                                           sigma=(0.3, 0.3, 0.3), alpha=2.5), (5, None), None)]
+    + [(f"gauss-p{p}-q{q}", _spec(p, quad="gauss", nq1d=q), None, None)
+       for p, q in [(1, 2), (2, 3), (2, 4), (3, 6), (4, 5), (4, 6), (5, 7), (7, 9), (8, 11)]]
+    + [("gauss-p3-jitter-sigma", _spec(3, quad="gauss", nq1d=5), (23, None), 8)]
+)
+
+
+@pytest.mark.parametrize("name,spec,jit,sseed", APPLY_CASES, ids=[c[0] for c in APPLY_CASES])
+def test_apply_f64(name, spec, jit, sseed):
+    announce(f"apply f64 {name}")
+    if jit is not None:
+        jit = (jit[0], jitter_scale(spec))
+    prob, A, M, K = oracle_problem(spec, sigma_seed=sseed, jitter=jit)
+    sigma = None if sseed is None else to_dev(prob.sigma)
+    op, _ = _op(spec, jitter=jit, sigma=sigma)
+    x = synth.uniform(100, spec.n_dof)
+    y = to_np(op.apply(to_dev(x)))
+    assert rel_l2(y, A @ x) <= TOL64
+    ym = to_np(op.apply_mass(to_dev(x)))
+    assert rel_l2(ym, M @ x) <= TOL64
+    d = to_np(op.diagonal())
+    assert rel_l2(d, A.diagonal()) <= TOL64
+
+
+@pytest.mark.parametrize("p,quad,q", [(2, "gll", 0), (4, "gll", 0), (7, "gll", 0), (4, "gauss", 6)])
+def test_apply_f32(p, quad, q):
+    announce(f"apply f32 p{p} {quad}")
+    spec = _spec(p, quad=quad, nq1d=q)
+    prob, A, M, K = oracle_problem(spec)
+    op, _ = _op(spec, store_f32=True)
+    x = synth.uniform(101, spec.n_dof)
+    y = to_np(op.apply(to_dev(x, torch.float32)))
+    assert rel_l2(y, A @ x) <= TOL32
+    d = to_np(op.diagonal(torch.float32))
+    assert rel_l2(d, A.diagonal()) <= TOL32
+
+
+def test_apply_batch_sigma():
+    announce("apply batch of 3 sigma sets")
+    spec = _spec(3, (4, 3, 2))
+    sig = synth.element_sigma(31, 3, spec.n_elem)
+    box = mf.Box.from_spec(spec)
+    op = mf.Operator.from_spec(spec, box=box, sigma=to_dev(sig))
+    x = synth.uniform(102, (3, spec.n_dof))
+    y = to_np(op.apply(to_dev(x)))
+    for b in range(3):
+        A, _, _ = oop.Problem(spec, sigma=sig[b]).assemble()
+        assert rel_l2(y[b], A @ x[b]) <= TOL64
+    # set_sigma recomputes the geometry
+    sig2 = sig[::-1].copy()
+    op.set_sigma(to_dev(sig2))
+    y2 = to_np(op.apply(to_dev(x)))
+    A0, _, _ = oop.Problem(spec, sigma=sig2[0]).assemble()
+    assert rel_l2(y2[0], A0 @ x[0]) <= TOL64
+
+
+def test_apply_sheet_orthotropic():
+    """Full orthotropic tensor with a sheet field (sigma_n != sigma_t)."""
+    announce("apply orthotropic sheet")
+    spec = _spec(3, (3, 2, 2)).with_(sigma=(0.17, 0.05, 0.019))
+    box = mf.Box.from_spec(spec)
+    m = omesh.box(spec)
+    sheet = np.stack([-m.fiber[:, 1], m.fiber[:, 0], 0.3 * np.ones(spec.n_dof)], axis=1)
+    op = mf.Operator.from_spec(spec, box=box, sheet=to_dev(sheet))
+    # oracle with the sheet: assemble through element_matrices
+    prob = oop.Problem(spec)
+    x = synth.uniform(103, spec.n_dof)
+    y_ref = np.zeros(spec.n_dof)
+    for el in prob.chunks():
+        X = prob.mesh.xyz[prob.mesh.elem_dof[el]]
+        geo = oop.geometry(X, prob.mesh.fiber[prob.mesh.elem_dof[el]],
+                           sheet[prob.mesh.elem_dof[el]], spec.p, prob.pts, prob.w)
+        Me, Ke = oop.element_matrices(geo, prob.sigma[el], spec.p, prob.pts, spec.alpha)
+        ye = np.einsum("eij,ej->ei", spec.alpha * Me + Ke, x[prob.elem_dof[el]])
+        np.add.at(y_ref, prob.elem_dof[el].reshape(-1), ye.reshape(-1))
+    assert rel_l2(to_np(op.apply(to_dev(x))), y_ref) <= TOL64
+
+
+# -------------------------------------------------------------- multigrid ---
+def _levels_oracle(spec, chain):
+    """Oracle level matrices and prolongations for a coarsening chain."""
+    probs = [oop.Problem(spec)]
+    Ps = []
+    cur, n, p = spec, spec.n, spec.p
+    for step in chain:
+        if step[0] == "p":
+            probs.append(oop.Problem(cur, dof_p=step[1]))
+            Ps.append(omg.prolongation_p(n, p, step[1]))
+            p = step[1]
+        else:
+            nc = tuple(k // 2 for k in n)
+            Ps.append(omg.prolongation_h(n, p))
+            cur = cur.with_(n=nc, shear_amp=cur.shear_amp / 2, p=p)
+            probs.append(oop.Problem(cur))
+            n = nc
+    mats = [pr.assemble()[0] for pr in probs]
+    return probs, mats, Ps
+
+
+CHAINS = {
+    "p4-2-1": (_spec(4, (4, 3, 2)), (("p", 2), ("p", 1))),
+    "h-p3": (_spec(3, (4, 2, 4)), (("h",), ("p", 1))),
+    "p7-3-1": (_spec(7, (2, 2, 1)), (("p", 3), ("p", 1))),
+}
+
+
+@pytest.mark.parametrize("name", list(CHAINS))
+def test_transfers(name):
+    announce(f"transfers {name}")
+    spec, chain = CHAINS[name]
+    probs, mats, Ps = _levels_oracle(spec, chain)
+    ops, mg = mf.hierarchy(spec, coarsening=chain, lambda_max=[1.0] * len(mats))
+    for l, P in enumerate(Ps):
+        xc = synth.uniform(200 + l, P.shape[1])
+        rf = synth.uniform(300 + l, P.shape[0])
+        assert rel_l2(to_np(mg.prolong(l, to_dev(xc))), P @ xc) <= TOL64
+        assert rel_l2(to_np(mg.restrict(l, to_dev(rf))), P.T @ rf) <= TOL64
+    for l, op in enumerate(ops):
+        x = synth.uniform(400 + l, op.n_dof)
+        assert rel_l2(to_np(op.apply(to_dev(x))), mats[l] @ x) <= TOL64
+
+
+@pytest.mark.parametrize("name", list(CHAINS))
+def test_vcycle_matches_oracle(name):
+    announce(f"vcycle {name}")
+    spec, chain = CHAINS[name]
+    probs, mats, Ps = _levels_oracle(spec, chain)
+    lam = [1.05 * osol.lanczos_lambda_max(A, 1 / A.diagonal(), synth.uniform(7, A.shape[0]))
+           for A in mats]
+    levels = [(A, 1 / A.diagonal(), l) for A, l in zip(mats, lam)]
+    ops, mg = mf.hierarchy(spec, coarsening=chain, lambda_max=lam, degree=3, coarse_degree=6)
+    b = synth.uniform(500, spec.n_dof)
+    z_ref = osol.vcycle(levels, Ps, b, 3, 6)
+    z = to_np(mg.vcycle(to_dev(b)))
+    assert rel_l2(z, z_ref) <= TOL64
+
+
+def test_lambda_estimate_bounds():
+    announce("lambda estimate")
+    spec, chain = CHAINS["p4-2-1"]
+    probs, mats, Ps = _levels_oracle(spec, chain)
+    ops, mg = mf.hierarchy(spec, coarsening=chain)
+    lam = mg.lambdas().numpy()[:, 0]
+    for A, l in zip(mats, lam):
+        d = A.diagonal()
+        S = (A.multiply(1 / np.sqrt(d)[:, None]).multiply(1 / np.sqrt(d)[None, :])).toarray()
+        emax = np.linalg.eigvalsh(S).max()
+        assert l <= emax * (1 + 1e-10) and l >= 0.8 * emax, (l, emax)
+
+
+# ------------------------------------------------------------------ solves ---
+def test_cg_c1():
+    announce("cg c1")
+    spec = synth.C1
+    prob, A, M, K = oracle_problem(spec)
+    op, _ = _op(spec)
+    f = synth.uniform(1, spec.n_dof)
+    x, info = mf.pcg(op, to_dev(f), rtol=1e-14, max_it=500)
+    x_ref = spla.spsolve(A.tocsc(), f)
+    assert rel_l2(to_np(x), x_ref) <= TOL64
+    assert info.status == [0]
+    # the BASELINE tolerance 1e-10 from x0 = 0
+    x10, info10 = mf.pcg(op, to_dev(f), rtol=1e-10, max_it=500)
+    r = f - A @ to_np(x10)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("name", ["p4-2-1", "h-p3"])
+def test_gmg_pcg(name):
+    announce(f"gmg pcg {name}")
+    spec, chain = CHAINS[name]
+    A = oracle_problem(spec)[1]
+    f = synth.uniform(2, spec.n_dof)
+    x_ref = spla.spsolve(A.tocsc(), f)
+    ops, mg = mf.hierarchy(spec, coarsening=chain, degree=3)
+    x, info = mf.pcg(ops[0], to_dev(f), mg=mg, rtol=1e-14, max_it=200)
+    assert rel_l2(to_np(x), x_ref) <= TOL64
+    assert info.iters[0] <= 30
+    x0, info0 = mf.pcg(ops[0], to_dev(f), rtol=1e-14, max_it=5000)
+    assert info.iters[0] < info0.iters[0]
+
+
+def test_mixed_precision_pcg():
+    announce("mixed pcg")
+    spec, chain = CHAINS["p4-2-1"]
+    A = oracle_problem(spec)[1]
+    f = synth.uniform(3, spec.n_dof)
+    x_ref = spla.spsolve(A.tocsc(), f)
+    ops, mg = mf.hierarchy(spec, coarsening=chain, degree=3, precision=torch.float32)
+    x, info = mf.pcg(ops[0], to_dev(f), mg=mg, rtol=1e-10, max_it=200)
+    assert info.status == [0]
+    assert rel_l2(to_np(x), x_ref) <= 1e-8
+    x2, info2 = mf.pcg(ops[0], to_dev(f), mg=mg, rtol=1e-14, max_it=200)
+    assert rel_l2(to_np(x2), x_ref) <= TOL64
+
+
+def test_batched_pcg_and_grad():
+    announce("batched pcg + grad")
+    spec = synth.BoxSpec(p=3, n=(3, 3, 2), length=(1.5, 1.5, 1.0), fiber=True,
+                         theta0=-1.0, theta1=1.0, sigma=synth.SLAB_SIGMA, alpha=28.0)
+    sig = synth.element_sigma(4, 2, spec.n_elem)
+    box = mf.Box.from_spec(spec)
+    op = mf.Operator.from_spec(spec, box=box, sigma=to_dev(sig))
+    f = synth.uniform(5, (2, spec.n_dof))
+    x, info = mf.pcg(op, to_dev(f), rtol=1e-14, max_it=2000)
+    for b in range(2):
+        prob = oop.Problem(spec, sigma=sig[b])
+        A, _, _ = prob.assemble()
+        assert rel_l2(to_np(x)[b], spla.spsolve(A.tocsc(), f[b])) <= TOL64
+        u = synth.uniform(6 + b, spec.n_dof)
+        w = synth.uniform(8 + b, spec.n_dof)
+        g_ref = oadj.grad_sigma(prob, u, w)
+        uu = np.stack([u if bb == b else np.zeros_like(u) for bb in range(2)])
+        ww = np.stack([w if bb == b else np.zeros_like(w) for bb in range(2)])
+        g = to_np(op.grad_sigma(to_dev(uu), to_dev(ww)))[b]
+        assert rel_l2(g, g_ref) <= TOL64
+
+
+def test_ionic_step():
+    announce("ionic step")
+    n = 5000
+    V = synth.uniform(9, n, -85.0, 30.0)
+    w = synth.uniform(10, n, 0.0, 1.5)
+    ist = synth.uniform(11, n, 0.0, 50.0)
+    m = synth.uniform(12, n, 0.1, 1.0)
+    b_ref, w_ref = oion.imex_rhs_and_gate(V, w, ist, m, 0.05, synth.CHI, synth.CM, synth.AP_PARAMS)
+    wd = to_dev(w)
+    b = mf.ap_imex_rhs(to_dev(V), wd, to_dev(m), 0.05, synth.CHI, synth.CM, synth.AP_PARAMS,
+                       i_stim=to_dev(ist))
+    assert rel_l2(to_np(b), b_ref) <= 1e-14
+    assert rel_l2(to_np(wd), w_ref) <= 1e-14
+
+
+# ------------------------------------------------------------------ errors ---
+def test_error_paths():
+    announce("error paths")
+    spec = _spec(2, (2, 2, 2))
+    box = mf.Box.from_spec(spec)
+    bad = box.xyz.clone()
+    bad[:, 0] = -bad[:, 0]  # mirrored map: det J < 0 everywhere
+    with pytest.raises(mf.MfsemError) as e:
+        mf.Operator.from_spec(spec, box=box, xyz=bad)
+    assert e.value.status == -3 and "element 0" in str(e.value)
+    with pytest.raises(mf.MfsemError) as e:
+        mf.Operator.from_spec(spec, box=box, quad="gll", nq1d=spec.p + 2)
+    assert e.value.status == -1
+    op = mf.Operator.from_spec(spec, box=box)
+    f = to_dev(synth.uniform(1, spec.n_dof))
+    x, info = mf.pcg(op, f, rtol=1e-14, max_it=1, check=False)
+    assert info.status == [-5] and info.iters == [1]
+    with pytest.raises(mf.MfsemError):
+        mf.pcg(op, f, rtol=1e-14, max_it=1)
+    fn = f.clone()
+    fn[3] = float("nan")
+    x, info = mf.pcg(op, fn, rtol=1e-10, max_it=10, check=False)
+    assert info.status == [-7]
+    with pytest.raises(ValueError):
+        op.apply(torch.zeros(3, device="cuda", dtype=torch.float64))
+    with pytest.raises(mf.MfsemError):
+        op.apply(torch.zeros(spec.n_dof, device="cuda", dtype=torch.float32))  # no FP32 geometry
