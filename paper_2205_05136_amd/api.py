@@ -50,7 +50,10 @@ class Box:
         L.check(lib.mfsem_box_counts(C.byref(self.desc), C.byref(ne), C.byref(nd)))
         self.p, self.n = p, tuple(n)
         self.n_elem, self.n_dof = ne.value, nd.value
-        self.device = torch.device(device)
+        device = torch.device(device)
+        if device.type == "cuda" and device.index is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = device
         P3 = (p + 1) ** 3
         self.elem_dof = torch.empty((self.n_elem, P3), dtype=torch.int32, device=device)
         self.xyz = torch.empty((self.n_dof, 3), dtype=torch.float64, device=device)
