@@ -1,0 +1,297 @@
+"""Benchmark of the matrix-free SEM-NI operator and its GMG-PCG solve on one GPU.
+
+Default workload: the sheared slab 20 x 7 x 3 mm with 40 x 14 x 6 hexahedra at
+p = 4, GLL quadrature (SEM-NI), anisotropic rotating-fiber conductivity,
+alpha = chi*Cm/dt = 28 (229,425 DOFs); FP64 apply and GMG-PCG with
+p-coarsening 4 -> 2 -> 1 and Chebyshev degree 3, random right-hand side.
+
+One timed step = one pass of the hot path on that input:
+  * R back-to-back operator applies y = A x (FP64; --apply-reps, default 20),
+  * one FP64 GMG-PCG solve A u = f to ||r||/||f|| <= 1e-10 from u0 = 0,
+  * one mixed-precision solve (FP32 V-cycle inside FP64 flexible CG), same tolerance.
+`value` is the apply throughput in GDOF/s (unique mesh nodes per second) from
+HIP events around the back-to-back applies inside the timed steps (so host
+launch gaps do not count); the PCG times are reported beside it.  Set-up (geometry, diagonals, eigenvalue estimates) is
+outside the timed region, as in the paper.
+
+Other workloads (--workload): slab-p{2..7}[-gauss] (the sheared slab refined to
+about 51M DOFs), c3 / c3-gauss (128 x 48 x 24 at p = 7).
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(spec, n_elem, n_dof, w, quad):
+    """Bytes an apply must move: x read, y write, the diagonal mass (SEM-NI) or
+    W|J| per point (SEM), the 6 stored G entries per quadrature point and the
+    element-to-node index."""
+    q3 = spec.q ** 3
+    P3 = (spec.p + 1) ** 3
+    g = 6 * n_elem * q3 * w
+    idx = 4 * n_elem * P3
+    if quad == "gll":
+        return 3 * w * n_dof + g + idx
+    return 2 * w * n_dof + w * n_elem * q3 + g + idx
+
+
+def algorithmic_flops(spec, n_elem, n_dof, quad):
+    P, q = spec.p + 1, spec.q
+    if quad == "gll":
+        return n_elem * (12 * P ** 4 + 15 * q ** 3) + 2 * n_dof
+    return n_elem * (4 * (q * P ** 3 + q * q * P * P + q ** 3 * P) + 12 * q ** 4 + 17 * q ** 3)
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter runs (profiles/counters.json),
+    or None when the kernel source changed since they were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2205_05136_amd", "csrc", "ax.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    try:
+        entry = json.load(open(os.path.join(ROOT, "profiles", "counters.json"))).get(
+            f"{kernel}|{workload}")
+    except (OSError, ValueError):
+        return None
+    if not entry or entry.get("source_sha") != sha:
+        return None
+    return int(entry["read_bytes"] + entry["write_bytes"])
+
+
+def workload(name):
+    import synth
+    if name == "c2":
+        return synth.C2, "c2: sheared slab 20x7x3 mm, 40x14x6 hexes, p=4, SEM-NI (GLL), rotating fibers"
+    if name.startswith("slab-p"):
+        parts = name.split("-")
+        p = int(parts[1][1:])
+        gauss = len(parts) > 2 and parts[2] == "gauss"
+        spec = synth.sweep(p, quad="gauss" if gauss else "gll", nq1d=p + 2 if gauss else 0)
+        return spec, (f"sheared slab at ~51M DOFs: {spec.n[0]}x{spec.n[1]}x{spec.n[2]} hexes, "
+                      f"p={p}, {'SEM (Gauss q=p+2)' if gauss else 'SEM-NI (GLL)'}")
+    if name == "c3":
+        return synth.C3_NI, "c3: sheared slab 128x48x24 hexes, p=7, SEM-NI (GLL)"
+    if name == "c3-gauss":
+        return synth.C3_SEM, "c3: sheared slab 128x48x24 hexes, p=7, SEM (Gauss q=9)"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(spec, budget_s=20.0):
+    """The oracle's matrix-based apply (assembled CSR SpMV, SciPy, one thread)
+    on the same mesh, timed on the host cores."""
+    import numpy as np
+    import synth
+    from oracle import operator as oop
+    if spec.n_dof > 3_000_000:
+        # too large to assemble: rows of A x one by one from the element matrices
+        x_fn = lambda g: np.sin(0.37 * np.asarray(g, dtype=np.float64))
+        rng = np.random.default_rng(0)
+        rows, t = 0, 0.0
+        while t < budget_s:
+            g = rng.integers(0, spec.n_dof, 16)
+            t1 = time.perf_counter()
+            oop.apply_rows(spec, x_fn, g)
+            t += time.perf_counter() - t1
+            rows += len(g)
+        return {"value": rows / t / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+                "sample": (f"oracle row-by-row apply (dense element matrices of the elements "
+                           f"around each DOF) on {rows} random rows of the full mesh in {t:.1f} s; "
+                           f"the assembled matrix would not fit in host memory")}
+    t0 = time.perf_counter()
+    prob = oop.Problem(spec)
+    A, _, _ = prob.assemble()
+    t_asm = time.perf_counter() - t0
+    x = synth.uniform(100, prob.n_dof)
+    reps, t_spmv = 0, 0.0
+    while t_spmv < budget_s and reps < 200:
+        t1 = time.perf_counter()
+        A @ x
+        t_spmv += time.perf_counter() - t1
+        reps += 1
+    per = t_spmv / reps
+    return {"value": prob.n_dof / per / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle assembled-CSR SpMV (SciPy, single thread) on the full workload "
+                       f"mesh, {reps} applies in {t_spmv:.1f} s ({per * 1e3:.2f} ms each); "
+                       f"element-matrix assembly {t_asm:.1f} s excluded; host has "
+                       f"{os.cpu_count()} logical CPUs")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also run an elementwise copy of 2 x N doubles (HBM counter reference)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has "
+              f"no multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2205_05136_amd as mf
+    import synth
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    spec, desc = workload(args.workload)
+    log(f"workload {args.workload}: {desc}; N = {spec.n_dof:,} DOFs, {spec.n_elem:,} elements")
+    dev = "cuda"
+    t0 = time.perf_counter()
+    coarsening = (("p", 2), ("p", 1)) if spec.p >= 3 else (("p", 1),)
+    do_pcg = not args.no_pcg
+    if do_pcg:
+        ops, mg32 = mf.hierarchy(spec, coarsening=coarsening, degree=3, precision=torch.float32)
+        op = ops[0]
+        mg64 = mf.Multigrid(ops, mg32.transfers, degree=3, precision=torch.float64)
+    else:
+        op = mf.Operator.from_spec(spec, store_f32=True)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    log(f"set-up {t_setup:.2f} s")
+
+    x = torch.as_tensor(synth.uniform(100, spec.n_dof), device=dev)
+    f = torch.as_tensor(synth.uniform(2, spec.n_dof), device=dev)
+    y = torch.empty_like(x)
+    x32 = x.float()
+    y32 = torch.empty_like(x32)
+    E = lambda: torch.cuda.Event(enable_timing=True)
+
+    R = args.apply_reps
+
+    def step(rec):
+        ev = [E() for _ in range(10)]
+        ev[0].record()
+        for _ in range(R):
+            op.apply(x, out=y)                 # full apply: clear y + operator kernel
+        ev[1].record()
+        y.zero_()
+        ev[2].record()
+        for _ in range(R):
+            op.apply_add(x, y)                 # the operator kernel alone
+        ev[3].record()
+        y32.zero_()
+        ev[4].record()
+        for _ in range(R):
+            op.apply_add(x32, y32)             # FP32 operator kernel
+        ev[5].record()
+        it64 = it32 = None
+        if do_pcg:
+            ev[6].record()
+            u64, i64 = mf.pcg(op, f, mg=mg64, rtol=1e-10, max_it=200)
+            ev[7].record()
+            u32, i32 = mf.pcg(op, f, mg=mg32, rtol=1e-10, max_it=200)
+            ev[8].record()
+            it64, it32 = i64.iters[0], i32.iters[0]
+            rec.setdefault("sol", (u64, u32))
+        rec.setdefault("ev", []).append(ev)
+        rec.setdefault("its", []).append((it64, it32))
+
+    warm = {}
+    for _ in range(args.warmup):
+        step(warm)
+    torch.cuda.synchronize()
+    rec = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall / args.steps * 1e3
+
+    def mean_ms(a, b):
+        return sum(ev[a].elapsed_time(ev[b]) for ev in rec["ev"]) / len(rec["ev"])
+
+    t_apply = mean_ms(0, 1) / R
+    t_kernel = mean_ms(2, 3) / R
+    t_kernel32 = mean_ms(4, 5) / R
+    N = spec.n_dof
+    gdofs = N / (t_apply * 1e-3) / 1e9
+    bytes64 = algorithmic_bytes(spec, spec.n_elem, N, 8, spec.quad)
+    bytes32 = algorithmic_bytes(spec, spec.n_elem, N, 4, spec.quad)
+    flops = algorithmic_flops(spec, spec.n_elem, N, spec.quad)
+    achieved = bytes64 / (t_kernel * 1e-3) / 1e9
+    kname = (f"ax_ni_kernel<double,{spec.p + 1}>" if spec.quad == "gll"
+             else f"ax_sem_kernel<double,{spec.p + 1},{spec.q}>")
+    out = {
+        "metric": "operator-apply GDOF/s and PCG time-to-1e-10, FP64 vs mixed, p=2..7",
+        "value": round(gdofs, 4),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n_dof": N, "n_elem": spec.n_elem, "p": spec.p,
+                   "quadrature": spec.quad, "nq1d": spec.q, "alpha": spec.alpha,
+                   "sigma_mS_per_mm": list(spec.sigma),
+                   "multigrid": "p " + "->".join([str(spec.p)] + [str(c[1]) for c in coarsening])
+                                + ", Chebyshev degree 3 on [0.08, 1.2]*lambda_max (10 CG steps)",
+                   "parallelism": "single GPU"},
+        "apply": {"reps_per_step": R, "fp64_ms": round(t_apply, 5), "fp64_kernel_ms": round(t_kernel, 5),
+                  "fp64_kernel_gdofs": round(N / (t_kernel * 1e-3) / 1e9, 3),
+                  "fp32_kernel_ms": round(t_kernel32, 5),
+                  "fp32_kernel_gdofs": round(N / (t_kernel32 * 1e-3) / 1e9, 3),
+                  "fp32_hbm_frac": round(bytes32 / (t_kernel32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "fp64_tflops": round(flops / (t_kernel * 1e-3) / 1e12, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(kname, args.workload),
+                     "kernel": kname,
+                     "bytes_per_launch": int(bytes64),
+                     "bytes_model": "8*(x + y + diag mass)*N + 48*n_elem*q^3 (G) + 4*n_elem*(p+1)^3 (index)"},
+    }
+    if do_pcg:
+        t64 = mean_ms(6, 7)
+        t32 = mean_ms(7, 8)
+        u64, u32 = rec["sol"]
+        r = f - op.apply(u64)
+        rel_res = float(torch.linalg.norm(r) / torch.linalg.norm(f))
+        rel_mixed = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+        lam64 = mg64.lambdas()[:, 0].tolist()
+        out["pcg"] = {"fp64_ms": round(t64, 4), "mixed_ms": round(t32, 4),
+                      "fp64_iters": rec["its"][0][0], "mixed_iters": rec["its"][0][1],
+                      "fp64_true_rel_residual": rel_res,
+                      "mixed_vs_fp64_rel_l2": rel_mixed,
+                      "lambda_max_per_level": [round(v, 5) for v in lam64],
+                      "tol": 1e-10, "x0": "zero", "setup_s": round(t_setup, 3)}
+    if args.copy_ref:
+        # y = x + 0: reads 8N and writes 8N bytes; its counter readings calibrate
+        # the FETCH_SIZE / WRITE_SIZE of the operator kernel
+        for _ in range(3):
+            torch.add(x, 0.0, out=y)
+        torch.cuda.synchronize()
+        out["copy_ref_bytes"] = {"read": 8 * N, "write": 8 * N}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -166,6 +166,11 @@ mfsem_status mfsem_op_set_sigma(mfsem_op* op, const double* sigma, void* stream)
 mfsem_status mfsem_op_apply(const mfsem_op* op, int32_t dtype, const void* x, void* y,
                             void* stream);
 
+/* y += A x: the same operator kernel without clearing y first (one launch;
+ * the global sum is an atomic add, so y may be any vector to add to).       */
+mfsem_status mfsem_op_apply_add(const mfsem_op* op, int32_t dtype, const void* x, void* y,
+                                void* stream);
+
 /* y = M x (the mass matrix alone, same quadrature). */
 mfsem_status mfsem_op_apply_mass(const mfsem_op* op, int32_t dtype, const void* x, void* y,
                                  void* stream);

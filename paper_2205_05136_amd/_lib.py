@@ -6,7 +6,8 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmfsem.so")
+# MFSEM_LIBRARY may point at another build of the same library (e.g. to compare builds)
+LIB_PATH = os.environ.get("MFSEM_LIBRARY") or os.path.join(_HERE, "libmfsem.so")
 
 MFSEM_OK, MFSEM_EINVAL, MFSEM_EUNSUPPORTED, MFSEM_EGEOMETRY = 0, -1, -2, -3
 MFSEM_EDEVICE, MFSEM_ENOCONV, MFSEM_EBREAKDOWN, MFSEM_ENONFINITE = -4, -5, -6, -7
@@ -80,6 +81,7 @@ PROTOTYPES = {
     "mfsem_op_set_alpha": (_ST, [_P, C.c_double]),
     "mfsem_op_set_sigma": (_ST, [_P, _P, _P]),
     "mfsem_op_apply": (_ST, [_P, C.c_int32, _P, _P, _P]),
+    "mfsem_op_apply_add": (_ST, [_P, C.c_int32, _P, _P, _P]),
     "mfsem_op_apply_mass": (_ST, [_P, C.c_int32, _P, _P, _P]),
     "mfsem_op_diagonal": (_ST, [_P, C.c_int32, _P, _P]),
     "mfsem_op_grad_sigma": (_ST, [_P, _P, _P, _P, _P]),

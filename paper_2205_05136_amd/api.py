@@ -160,6 +160,13 @@ class Operator:
         L.check(L.load().mfsem_op_apply(self.handle, self._dt(x), _ptr(x), _ptr(y), _stream(stream)))
         return y
 
+    def apply_add(self, x, y, stream=None):
+        """y += A x (mfsem_op_apply_add), one kernel launch."""
+        x, y = self._vec(x), self._vec(y)
+        L.check(L.load().mfsem_op_apply_add(self.handle, self._dt(x), _ptr(x), _ptr(y),
+                                            _stream(stream)))
+        return y
+
     def apply_mass(self, x, out=None):
         x = self._vec(x)
         y = torch.empty_like(x) if out is None else self._vec(out)
@@ -213,6 +220,7 @@ class Multigrid:
                 trs[i] = L.TransferDesc(kind=L.MFSEM_TRANSFER_H, parent=parent.data_ptr(),
                                         child=child.data_ptr())
         self._trs = trs
+        self.transfers = list(transfers)
         lam = None
         if lambda_max is not None:
             vals = [float(v) for v in torch.as_tensor(lambda_max, dtype=torch.float64).reshape(-1)]

@@ -31,32 +31,33 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wno-unknown-warning-option"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-    if src.endswith(".cpp"):
-        cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-x", "c++", "-c",
-               os.path.join(CSRC, src), "-o", obj, "-D__HIP_PLATFORM_AMD__"]
+def _compile(src: str, csrc: str = CSRC, build_dir: str = BUILD_DIR) -> str:
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(PKG, "..", "include"), "-c",
+           os.path.join(csrc, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC,
+          out: str = OUT) -> str:
+    """Compile the sources in `csrc` and link them into `out`."""
+    build_dir = BUILD_DIR if csrc == CSRC else os.path.join(os.path.dirname(out), "_build")
+    os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = OUT + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, csrc, build_dir), SOURCES))
+    tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {OUT}")
-    return OUT
+        print(f"built {out}")
+    return out
 
 
 def clean() -> None:
@@ -66,9 +67,11 @@ def clean() -> None:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("--src", default=CSRC, help="source directory (default: the package's csrc)")
+    ap.add_argument("--out", default=OUT, help="library to write")
     args = ap.parse_args()
     try:
-        build(args.j, verbose=True)
+        build(args.j, verbose=True, csrc=os.path.abspath(args.src), out=os.path.abspath(args.out))
     except RuntimeError as e:
         print(e, file=sys.stderr)
         sys.exit(1)

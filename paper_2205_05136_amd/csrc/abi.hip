@@ -108,10 +108,12 @@ void check_op(const mfsem_op* op, int dtype) {
   else require(op->G32 != nullptr, "operator has no FP32 geometry (store_f32 = 0)");
 }
 
-void read_bad_flag(const mfsem_op& op, hipStream_t s) {
-  unsigned long long bad = 0;
-  MFSEM_HIP(hipMemcpyAsync(&bad, op.bad, sizeof(bad), hipMemcpyDeviceToHost, s));
+void read_bad_flag(mfsem_op& op, hipStream_t s) {
+  unsigned long long flags[2] = {0, 0};
+  MFSEM_HIP(hipMemcpyAsync(flags, op.bad, sizeof(flags), hipMemcpyDeviceToHost, s));
   MFSEM_HIP(hipStreamSynchronize(s));
+  op.use_det = flags[1] == 0;
+  const unsigned long long bad = flags[0];
   if (bad != ~0ull) {
     const unsigned long long e = bad / op.nq3, k = bad % op.nq3;
     fail(MFSEM_EGEOMETRY, "det J <= 0 in element " + std::to_string(e) + " at quadrature point " +
@@ -133,7 +135,9 @@ void op_layout(mfsem_op& op, Arena& a) {
   }
   op.tab64 = a.take_n<double>(op.off.total);
   op.tab32 = a.take_n<float>(op.off.total);
-  op.bad = a.take_n<unsigned long long>(1);
+  if (op.d.store_f64) op.idet64 = a.take_n<double>(B * ne);
+  if (op.d.store_f32) op.idet32 = a.take_n<float>(B * ne);
+  op.bad = a.take_n<unsigned long long>(2);
   op.sigma_copy = op.d.sigma ? a.take_n<double>(B * ne * 3) : nullptr;
 }
 
@@ -264,6 +268,20 @@ mfsem_status mfsem_op_apply(const mfsem_op* op, int32_t dtype, const void* x, vo
       launch_apply<double>(*op, static_cast<const double*>(x), static_cast<double*>(y), op->alpha, true, s);
     else
       launch_apply<float>(*op, static_cast<const float*>(x), static_cast<float*>(y), op->alpha, true, s);
+  });
+}
+
+mfsem_status mfsem_op_apply_add(const mfsem_op* op, int32_t dtype, const void* x, void* y,
+                                void* stream) {
+  return guarded([&] {
+    check_op(op, dtype);
+    require(x && y, "x or y is NULL");
+    require(x != y, "x and y must not alias");
+    hipStream_t s = as_stream(stream);
+    if (dtype == MFSEM_F64)
+      launch_apply<double>(*op, static_cast<const double*>(x), static_cast<double*>(y), op->alpha, true, s, true);
+    else
+      launch_apply<float>(*op, static_cast<const float*>(x), static_cast<float*>(y), op->alpha, true, s, true);
   });
 }
 

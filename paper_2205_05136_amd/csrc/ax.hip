@@ -40,8 +40,8 @@ struct NiCfg {
 template <typename T, int P, bool STIFF>
 __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
     int64_t n_elem, int64_t n_dof, const int32_t* __restrict__ ed, const T* __restrict__ G,
-    const T* __restrict__ WJ, T alpha, const T* __restrict__ Dtab, const T* __restrict__ x,
-    T* __restrict__ y) {
+    const T* __restrict__ WJ, const T* __restrict__ idet, T alpha, const T* __restrict__ Dtab,
+    const T* __restrict__ wtab, const T* __restrict__ x, T* __restrict__ y) {
   using C = NiCfg<P>;
   constexpr int P2 = C::P2, P3 = C::P3, NE = C::NE;
   __shared__ T sD[P * P];
@@ -62,18 +62,24 @@ __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
 
   T u[P];
   int gi[P];
+  if (!STIFF) {
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < P; ++c) gi[c] = ed[e * P3 + c * P2 + ab];
+#pragma unroll
+      for (int c = 0; c < P; ++c) atomic_add(&y[gi[c]], alpha * WJ[e * P3 + c * P2 + ab] * x[gi[c]]);
+    }
+    return;
+  }
+  // G (6 values per point, the dominant HBM stream) is loaded after the
+  // derivative phase: loading it up front raises the register count and lowers
+  // occupancy more than the overlap gains at moderate p.
+  T g[6][P];
   if (active) {
 #pragma unroll
     for (int c = 0; c < P; ++c) gi[c] = ed[e * P3 + c * P2 + ab];
 #pragma unroll
     for (int c = 0; c < P; ++c) u[c] = x[gi[c]];
-  }
-  if (!STIFF) {
-    if (active) {
-#pragma unroll
-      for (int c = 0; c < P; ++c) atomic_add(&y[gi[c]], alpha * WJ[e * P3 + c * P2 + ab] * u[c]);
-    }
-    return;
   }
   T* su = sU + le * P3;
   T* sv = sV + le * P3;
@@ -103,16 +109,32 @@ __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
 
   T ft[P], out[P];
   if (active) {
-    const T* Ge = G + (int64_t)bt * n_elem * 6 * P3 + e * 6 * P3;
+    // mass weight W|J| = det(G) / (W^2 det(sigma)) when available, else stored
+    const T* Ge = G + ((int64_t)bt * n_elem + e) * 6 * P3 + ab;
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int c = 0; c < P; ++c) g[m][c] = Ge[m * P3 + c * P2];
+    const T id = idet ? idet[(int64_t)bt * n_elem + e] : T(0);
+    const T wab = idet ? wtab[ia] * wtab[ib] : T(0);
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       const int q = c * P2 + ab;
-      const T g00 = Ge[q], g01 = Ge[P3 + q], g02 = Ge[2 * P3 + q];
-      const T g11 = Ge[3 * P3 + q], g12 = Ge[4 * P3 + q], g22 = Ge[5 * P3 + q];
+      const T g00 = g[0][c], g01 = g[1][c], g02 = g[2][c];
+      const T g11 = g[3][c], g12 = g[4][c], g22 = g[5][c];
       su[q] = g00 * ur[c] + g01 * us[c] + g02 * ut[c];
       sv[q] = g01 * ur[c] + g11 * us[c] + g12 * ut[c];
       ft[c] = g02 * ur[c] + g12 * us[c] + g22 * ut[c];
-      out[c] = (alpha != T(0)) ? alpha * WJ[e * P3 + q] * u[c] : T(0);
+      T wj;
+      if (idet) {
+        const T W = wab * wtab[c];
+        const T dG = g00 * (g11 * g22 - g12 * g12) - g01 * (g01 * g22 - g12 * g02) +
+                     g02 * (g01 * g12 - g11 * g02);
+        wj = dG * id / (W * W);
+      } else {
+        wj = WJ[e * P3 + q];
+      }
+      out[c] = alpha * wj * u[c];
     }
   }
   __syncthreads();
@@ -341,13 +363,21 @@ const double* WJ_of<double>(const mfsem_op& op) { return op.WJ64; }
 template <>
 const float* WJ_of<float>(const mfsem_op& op) { return op.WJ32; }
 
+template <typename T>
+const T* idet_of(const mfsem_op& op);
+template <>
+const double* idet_of<double>(const mfsem_op& op) { return op.idet64; }
+template <>
+const float* idet_of<float>(const mfsem_op& op) { return op.idet32; }
+
 template <typename T, int P, bool STIFF>
 void run_ni(const mfsem_op& op, const T* x, T* y, T alpha, hipStream_t s) {
   using C = NiCfg<P>;
   const unsigned nb = blocks_for(op.d.n_elem, C::NE);
+  const T* tab = tables_of<T>(op);
   ax_ni_kernel<T, P, STIFF><<<dim3(nb, op.d.batch), dim3(C::THREADS), 0, s>>>(
-      op.d.n_elem, op.d.n_dof, op.d.elem_dof, G_of<T>(op), WJ_of<T>(op), alpha,
-      tables_of<T>(op) + op.off.Db, x, y);
+      op.d.n_elem, op.d.n_dof, op.d.elem_dof, G_of<T>(op), WJ_of<T>(op),
+      op.use_det ? idet_of<T>(op) : nullptr, alpha, tab + op.off.Db, tab + op.off.w, x, y);
   MFSEM_LAUNCH("ax_ni_kernel");
 }
 
@@ -471,8 +501,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_kernel(
 
 template <typename T>
 void launch_apply(const mfsem_op& op, const T* x, T* y, double alpha, bool stiffness,
-                  hipStream_t s) {
-  zero<T>(y, op.d.n_dof * op.d.batch, s);
+                  hipStream_t s, bool accumulate) {
+  if (!accumulate) zero<T>(y, op.d.n_dof * op.d.batch, s);
   if (op.d.n_elem == 0) return;
   if (stiffness) dispatch<T, true>(op, x, y, (T)alpha, s);
   else dispatch<T, false>(op, x, y, (T)alpha, s);
@@ -490,9 +520,9 @@ void launch_diag(const mfsem_op& op, T* d, hipStream_t s) {
 }
 
 template void launch_apply<double>(const mfsem_op&, const double*, double*, double, bool,
-                                   hipStream_t);
+                                   hipStream_t, bool);
 template void launch_apply<float>(const mfsem_op&, const float*, float*, double, bool,
-                                  hipStream_t);
+                                  hipStream_t, bool);
 template void launch_diag<double>(const mfsem_op&, double*, hipStream_t);
 template void launch_diag<float>(const mfsem_op&, float*, hipStream_t);
 

@@ -38,6 +38,8 @@ struct GeomArgs {
   double* WJ64;           // [n_elem][Q^3] or null
   float* G32;
   float* WJ32;
+  double* idet64;         // [batch][n_elem] 1/det(sigma_e) or null
+  float* idet32;
   unsigned long long* bad;
 };
 
@@ -65,6 +67,19 @@ __global__ __launch_bounds__(GEOM_THREADS) void geom_kernel(GeomArgs a) {
     sDm[i] = a.tab[a.oDm + i];
   }
   for (int i = tid; i < Q; i += blockDim.x) sW[i] = a.tab[a.ow + i];
+  // det(sigma_e): the eigenvalues of the tensor are (sigma_l, sigma_t, sigma_n)
+  // with a sheet, (sigma_l, sigma_t, sigma_t) with a fiber only, sigma_t (x3) without
+  for (int bt = tid; bt < a.batch; bt += blockDim.x) {
+    double sl = a.s0, st = a.s1, sv = a.s2;
+    if (a.sigma) {
+      const double* sp = a.sigma + ((int64_t)bt * a.n_elem + e) * 3;
+      sl = sp[0]; st = sp[1]; sv = sp[2];
+    }
+    const double dsig = !a.fiber ? st * st * st : (!a.sheet ? sl * st * st : sl * st * sv);
+    if (!(dsig > 0.0) || !isfinite(1.0 / dsig)) atomicAdd(a.bad + 1, 1ull);
+    if (a.idet64) a.idet64[(int64_t)bt * a.n_elem + e] = 1.0 / dsig;
+    if (a.idet32) a.idet32[(int64_t)bt * a.n_elem + e] = (float)(1.0 / dsig);
+  }
   __syncthreads();
 
   for (int k = tid; k < Q3; k += blockDim.x) {
@@ -190,8 +205,11 @@ void run_geometry(mfsem_op& op, hipStream_t s) {
   a.WJ64 = op.WJ64;
   a.G32 = op.G32;
   a.WJ32 = op.WJ32;
+  a.idet64 = op.idet64;
+  a.idet32 = op.idet32;
   a.bad = op.bad;
   vfill<unsigned long long>(op.bad, 1, ~0ull, s);
+  vfill<unsigned long long>(op.bad + 1, 1, 0ull, s);
   if (op.d.n_elem == 0) return;
   // one workgroup per element; the grid's x dimension holds up to 2^31-1
   geom_kernel<<<dim3((unsigned)op.d.n_elem), dim3(GEOM_THREADS), 0, s>>>(a);

@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mfsem.h"
+#include "mfsem.h"
 
 namespace mfsem {
 
@@ -98,7 +98,14 @@ struct mfsem_op {
   float* WJ32 = nullptr;
   double* tab64 = nullptr; // 1D tables
   float* tab32 = nullptr;
-  unsigned long long* bad = nullptr;  // first failing (element, point) of the geometry
+  // 1/det(sigma_e) per member and element: the apply recovers W|J| at a point
+  // from det G = (W|J|)^3 |J|^{-2} det(sigma) = W^3 |J| det(sigma), so the mass
+  // term needs no stored W|J| (used when every det(sigma_e) > 0)
+  double* idet64 = nullptr;  // [batch][n_elem]
+  float* idet32 = nullptr;
+  bool use_det = false;
+  // [0]: first failing (element, point) of the geometry; [1]: elements with det(sigma) <= 0
+  unsigned long long* bad = nullptr;
   double* sigma_copy = nullptr;       // [batch][n_elem][3] (kept for set_sigma / grad)
   mfsem::TableOffsets off;
   std::vector<double> tab_host;
@@ -113,7 +120,7 @@ void run_geometry(mfsem_op& op, hipStream_t s);  // fills G/WJ and the bad flag
 
 template <typename T>
 void launch_apply(const mfsem_op& op, const T* x, T* y, double alpha, bool stiffness,
-                  hipStream_t s);
+                  hipStream_t s, bool accumulate = false);
 template <typename T>
 void launch_diag(const mfsem_op& op, T* d, hipStream_t s);
 void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, double* g,

@@ -1,0 +1,144 @@
+"""GPU tests of the workflows around the hot path: autograd through apply and
+solve (adjoint), the monodomain time loop, and parity at full workload sizes
+(whole-vector parity on c2; sampled rows on the 51M-DOF p = 7 slab)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import synth
+from gpu_common import announce, rel_l2, to_dev, to_np
+from oracle import adjoint as oadj
+from oracle import ionic as oion
+from oracle import operator as oop
+from oracle import solvers as osol
+
+pytestmark = pytest.mark.gpu
+
+mf = pytest.importorskip("paper_2205_05136_amd")
+from paper_2205_05136_amd import autograd as ag  # noqa: E402
+from paper_2205_05136_amd import monodomain as md  # noqa: E402
+
+GSPEC = synth.BoxSpec(p=3, n=(4, 3, 2), length=(2.0, 1.5, 1.0), fiber=True, theta0=-1.0,
+                      theta1=1.0, sigma=synth.SLAB_SIGMA, alpha=28.0)
+
+
+def test_apply_autograd_matches_oracle():
+    announce("autograd apply")
+    spec = GSPEC
+    sig = synth.element_sigma(40, 2, spec.n_elem)
+    box = mf.Box.from_spec(spec)
+    op = mf.Operator.from_spec(spec, box=box, sigma=to_dev(sig))
+    u = to_dev(synth.uniform(41, (2, spec.n_dof))).requires_grad_(True)
+    w = synth.uniform(42, (2, spec.n_dof))
+    s = to_dev(sig).requires_grad_(True)
+    y = ag.apply(s, u, op)
+    (y * to_dev(w)).sum().backward()
+    for b in range(2):
+        prob = oop.Problem(spec, sigma=sig[b])
+        A, _, _ = prob.assemble()
+        assert rel_l2(to_np(y)[b], A @ to_np(u)[b]) <= 1e-12
+        assert rel_l2(to_np(u.grad)[b], A @ w[b]) <= 1e-12
+        g_ref = oadj.grad_sigma(prob, to_np(u)[b], w[b])
+        assert rel_l2(to_np(s.grad)[b], g_ref) <= 1e-12
+
+
+def test_solve_adjoint_vs_oracle_and_finite_differences():
+    announce("autograd solve + FD")
+    spec = GSPEC
+    sig = synth.element_sigma(43, 2, spec.n_elem)
+    f = synth.uniform(44, (2, spec.n_dof))
+    ut = 0.01 * synth.uniform(45, (2, spec.n_dof))
+    solver = ag.Solver(spec, batch=2, rtol=1e-14, max_it=300)
+    s = to_dev(sig).requires_grad_(True)
+    fd_ = to_dev(f).requires_grad_(True)
+    u = ag.solve(s, fd_, solver)
+    L = 0.5 * ((u - to_dev(ut)) ** 2).sum()
+    L.backward()
+    g = to_np(s.grad)
+    for b in range(2):
+        prob = oop.Problem(spec, sigma=sig[b])
+        Lb, g_ref, lam, u_ref = oadj.loss_and_grad(prob, f[b], ut[b])
+        assert rel_l2(to_np(u)[b], u_ref) <= 1e-12
+        assert rel_l2(g[b], g_ref) <= 1e-10
+        assert rel_l2(to_np(fd_.grad)[b], lam) <= 1e-10
+
+    def loss(sig_np):
+        with torch.no_grad():
+            uu = ag.solve(to_dev(sig_np), to_dev(f), solver)
+            return 0.5 * float(((uu - to_dev(ut)) ** 2).sum())
+
+    h = 1e-6
+    for (b, e, c) in [(0, 0, 0), (0, 7, 1), (1, 13, 0), (1, 23, 1)]:
+        sp_, sm_ = sig.copy(), sig.copy()
+        sp_[b, e, c] += h
+        sm_[b, e, c] -= h
+        fd = (loss(sp_) - loss(sm_)) / (2 * h)
+        assert abs(fd - g[b, e, c]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (b, e, c, fd, g[b, e, c])
+
+
+def test_monodomain_steps_match_oracle():
+    announce("monodomain 30 steps")
+    spec = synth.slab(3, (6, 3, 2)).with_(length=(3.0, 1.5, 1.0))
+    prm = synth.AP_PARAMS
+    dt = 0.05
+    stim = md.Stimulus(lo=(0, 0, 0), hi=(1.0, 1.0, 1.0), amplitude=50.0, duration=1.0)
+    sim = md.Monodomain(spec, dt, synth.CHI, synth.CM, prm, stim, precision=torch.float64,
+                        rtol=1e-14)
+    # oracle: the same scheme with explicit matrices and direct solves
+    ospec = spec.with_(alpha=synth.CHI * synth.CM / dt)
+    prob = oop.Problem(ospec)
+    A, M, _ = prob.assemble()
+    m = M.diagonal()
+    X = prob.mesh.xyz
+    inside = np.all((X >= 0.0) & (X <= 1.0), axis=1)
+    istim = inside * 50.0
+    V = np.full(prob.n_dof, prm["v_rest"])
+    w = np.zeros(prob.n_dof)
+    Ainv = spla.factorized(A.tocsc())
+    t = 0.0
+    for n in range(30):
+        b, w = oion.imex_rhs_and_gate(V, w, istim if t < 1.0 else 0.0 * istim, m, dt,
+                                      synth.CHI, synth.CM, prm)
+        V = Ainv(b)
+        t += dt
+        sim.step()
+    assert V.max() > -70.0  # the stimulus has depolarised part of the slab
+    assert rel_l2(to_np(sim.V), V) <= 1e-9
+    assert rel_l2(to_np(sim.w), w) <= 1e-9
+
+
+def test_c2_full_size_parity():
+    announce("c2 full size apply + GMG-PCG")
+    spec = synth.C2
+    prob = oop.Problem(spec)
+    A, _, _ = prob.assemble()
+    ops, mg = mf.hierarchy(spec, coarsening=(("p", 2), ("p", 1)), degree=3)
+    x = synth.uniform(100, spec.n_dof)
+    assert rel_l2(to_np(ops[0].apply(to_dev(x))), A @ x) <= 1e-12
+    f = synth.uniform(2, spec.n_dof)
+    u, info = mf.pcg(ops[0], to_dev(f), mg=mg, rtol=1e-10, max_it=100)
+    r = f - A @ to_np(u)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(f)
+    # both sides solved to 1e-14: they agree within kappa(A) * 1e-14 (kappa < 100 here)
+    u2, _ = mf.pcg(ops[0], to_dev(f), mg=mg, rtol=1e-14, max_it=100)
+    x_ref, it, _ = osol.cg(A, f, rtol=1e-14)
+    assert rel_l2(to_np(u2), x_ref) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["slab-p7-51M", "slab-p4-gauss-51M"])
+def test_full_size_sampled_rows(name):
+    """At the 51M-DOF workload size, in the benchmark's launch configuration:
+    rows of A x against the oracle's element matrices, x_g = sin(0.37 g)."""
+    announce(f"sampled rows {name}")
+    spec = synth.sweep(7) if name == "slab-p7-51M" else synth.sweep(4, quad="gauss", nq1d=6)
+    op = mf.Operator.from_spec(spec)
+    g = torch.arange(spec.n_dof, device="cuda", dtype=torch.float64)
+    x = torch.sin(0.37 * g)
+    y = op.apply(x)
+    rng = np.random.default_rng(1)
+    rows = np.concatenate([rng.integers(0, spec.n_dof, 24), [0, spec.n_dof - 1]])
+    ref = oop.apply_rows(spec, lambda gg: np.sin(0.37 * np.asarray(gg, dtype=np.float64)), rows)
+    got = to_np(y[torch.as_tensor(rows, device="cuda")])
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(got - ref)) <= 1e-12 * scale, (got - ref)
