@@ -139,6 +139,10 @@ typedef struct {
   double alpha;                /* mass coefficient, >= 0 */
   int32_t store_f64;           /* build FP64 geometry (needed by FP64 calls) */
   int32_t store_f32;           /* build FP32 geometry (needed by FP32 calls) */
+  int32_t lattice[3];          /* elements per axis when elem_dof is the structured box
+                                  numbering of mfsem_box_generate (checked at create;
+                                  EINVAL if it is not), enabling the brick kernels;
+                                  {0,0,0} for any other mesh                           */
 } mfsem_op_desc;
 
 /* Workspace an operator needs. [host] */

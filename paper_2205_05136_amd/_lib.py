@@ -37,7 +37,8 @@ class OpDesc(C.Structure):
                 ("map_p", C.c_int32), ("map_elem_dof", C.c_void_p), ("n_map_nodes", C.c_int64),
                 ("map_xyz", C.c_void_p), ("fiber", C.c_void_p), ("sheet", C.c_void_p),
                 ("sigma", C.c_void_p), ("sigma_const", C.c_double * 3), ("batch", C.c_int32),
-                ("alpha", C.c_double), ("store_f64", C.c_int32), ("store_f32", C.c_int32)]
+                ("alpha", C.c_double), ("store_f64", C.c_int32), ("store_f32", C.c_int32),
+                ("lattice", C.c_int32 * 3)]
 
 
 class TransferDesc(C.Structure):

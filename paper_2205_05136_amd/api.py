@@ -91,7 +91,7 @@ class Operator:
 
     def __init__(self, dofs: Box, geometry: Box | None = None, quad="gll", nq1d=0, sigma=None,
                  sigma_const=(1.0, 1.0, 1.0), batch=1, alpha=1.0, store_f64=True,
-                 store_f32=False, xyz=None, fiber="geometry", sheet=None):
+                 store_f32=False, xyz=None, fiber="geometry", sheet=None, structured=True):
         lib = L.load()
         geo = geometry or dofs
         self.dofs, self.geometry = dofs, geo
@@ -115,7 +115,8 @@ class Operator:
             map_p=geo.p, map_elem_dof=geo.elem_dof.data_ptr(), n_map_nodes=geo.n_dof,
             map_xyz=self.xyz.data_ptr(), fiber=_ptr(self.fiber).value, sheet=_ptr(sheet).value,
             sigma=_ptr(sigma).value, sigma_const=(C.c_double * 3)(*sigma_const), batch=batch,
-            alpha=alpha, store_f64=int(store_f64), store_f32=int(store_f32))
+            alpha=alpha, store_f64=int(store_f64), store_f32=int(store_f32),
+            lattice=(C.c_int32 * 3)(*(dofs.n if structured else (0, 0, 0))))
         nbytes = C.c_size_t()
         L.check(lib.mfsem_op_workspace_bytes(C.byref(self.desc), C.byref(nbytes)))
         self.ws = _workspace(nbytes.value, self.device)

@@ -87,6 +87,15 @@ void validate_op(const mfsem_op_desc* d) {
   if (!d->sigma)
     for (int i = 0; i < 3; ++i)
       require(std::isfinite(d->sigma_const[i]), "sigma_const must be finite");
+  if (d->lattice[0] || d->lattice[1] || d->lattice[2]) {
+    require(d->lattice[0] > 0 && d->lattice[1] > 0 && d->lattice[2] > 0,
+            "lattice counts must all be positive (or all zero)");
+    require((int64_t)d->lattice[0] * d->lattice[1] * d->lattice[2] == d->n_elem,
+            "lattice counts do not multiply to n_elem");
+    const int64_t nd = ((int64_t)d->p * d->lattice[0] + 1) * ((int64_t)d->p * d->lattice[1] + 1) *
+                       ((int64_t)d->p * d->lattice[2] + 1);
+    require(nd == d->n_dof, "lattice counts do not give n_dof");
+  }
 }
 
 void op_init(mfsem_op& op, const mfsem_op_desc* d) {
@@ -99,6 +108,8 @@ void op_init(mfsem_op& op, const mfsem_op_desc* d) {
   op.nq3 = (int64_t)op.Q * op.Q * op.Q;
   op.alpha = d->alpha;
   op.off = table_offsets(op.P, op.Q, op.Pm);
+  op.structured = d->lattice[0] > 0;
+  for (int i = 0; i < 3; ++i) op.lat[i] = d->lattice[i];
 }
 
 void check_op(const mfsem_op* op, int dtype) {
@@ -109,10 +120,13 @@ void check_op(const mfsem_op* op, int dtype) {
 }
 
 void read_bad_flag(mfsem_op& op, hipStream_t s) {
-  unsigned long long flags[2] = {0, 0};
+  unsigned long long flags[3] = {0, 0, 0};
   MFSEM_HIP(hipMemcpyAsync(flags, op.bad, sizeof(flags), hipMemcpyDeviceToHost, s));
   MFSEM_HIP(hipStreamSynchronize(s));
   op.use_det = flags[1] == 0;
+  if (op.structured && flags[2] != 0)
+    fail(MFSEM_EINVAL, "elem_dof does not follow the structured numbering of the given lattice (" +
+                           std::to_string(flags[2]) + " element nodes differ)");
   const unsigned long long bad = flags[0];
   if (bad != ~0ull) {
     const unsigned long long e = bad / op.nq3, k = bad % op.nq3;
@@ -137,7 +151,7 @@ void op_layout(mfsem_op& op, Arena& a) {
   op.tab32 = a.take_n<float>(op.off.total);
   if (op.d.store_f64) op.idet64 = a.take_n<double>(B * ne);
   if (op.d.store_f32) op.idet32 = a.take_n<float>(B * ne);
-  op.bad = a.take_n<unsigned long long>(2);
+  op.bad = a.take_n<unsigned long long>(3);
   op.sigma_copy = op.d.sigma ? a.take_n<double>(B * ne * 3) : nullptr;
 }
 
@@ -223,6 +237,7 @@ mfsem_status mfsem_op_create(const mfsem_op_desc* d, void* ws, size_t ws_bytes, 
                                (size_t)d->batch * d->n_elem * 3 * sizeof(double),
                                hipMemcpyDeviceToDevice, s));
     run_geometry(*op, s);
+    if (op->structured) launch_lattice_check(*op, op->bad + 2, s);
     read_bad_flag(*op, s);
     *out = op;
   });

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
   // G (6 values per point, the dominant HBM stream) is loaded after the
   // derivative phase: loading it up front raises the register count and lowers
   // occupancy more than the overlap gains at moderate p.
-  T g[6][P];
+  T g[P][6];
   if (active) {
 #pragma unroll
     for (int c = 0; c < P; ++c) gi[c] = ed[e * P3 + c * P2 + ab];
@@ -110,18 +110,16 @@ __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
   T ft[P], out[P];
   if (active) {
     // mass weight W|J| = det(G) / (W^2 det(sigma)) when available, else stored
-    const T* Ge = G + ((int64_t)bt * n_elem + e) * 6 * P3 + ab;
+    const T* Ge = G + (((int64_t)bt * n_elem + e) * P3 + ab) * 6;
 #pragma unroll
-    for (int m = 0; m < 6; ++m)
-#pragma unroll
-      for (int c = 0; c < P; ++c) g[m][c] = Ge[m * P3 + c * P2];
+    for (int c = 0; c < P; ++c) load_g6(Ge + c * P2 * 6, g[c]);
     const T id = idet ? idet[(int64_t)bt * n_elem + e] : T(0);
     const T wab = idet ? wtab[ia] * wtab[ib] : T(0);
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       const int q = c * P2 + ab;
-      const T g00 = g[0][c], g01 = g[1][c], g02 = g[2][c];
-      const T g11 = g[3][c], g12 = g[4][c], g22 = g[5][c];
+      const T g00 = g[c][0], g01 = g[c][1], g02 = g[c][2];
+      const T g11 = g[c][3], g12 = g[c][4], g22 = g[c][5];
       su[q] = g00 * ur[c] + g01 * us[c] + g02 * ut[c];
       sv[q] = g01 * ur[c] + g11 * us[c] + g12 * ut[c];
       ft[c] = g02 * ur[c] + g12 * us[c] + g22 * ut[c];
@@ -261,12 +259,14 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS)) void ax_sem_kernel(
     __syncthreads();
     T fz[Q];
     if (active) {
-      const T* Ge = G + (int64_t)bt * n_elem * 6 * Q3 + e * 6 * Q3;
+      const T* Ge = G + ((int64_t)bt * n_elem + e) * 6 * Q3;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         const int q = k * Q2 + j * Q + i;
-        const T g00 = Ge[q], g01 = Ge[Q3 + q], g02 = Ge[2 * Q3 + q];
-        const T g11 = Ge[3 * Q3 + q], g12 = Ge[4 * Q3 + q], g22 = Ge[5 * Q3 + q];
+        T g6[6];
+        load_g6(Ge + (int64_t)q * 6, g6);
+        const T g00 = g6[0], g01 = g6[1], g02 = g6[2];
+        const T g11 = g6[3], g12 = g6[4], g22 = g6[5];
         b3[q] = g00 * dx[k] + g01 * dy[k] + g02 * dz[k];
         b2[q] = g01 * dx[k] + g11 * dy[k] + g12 * dz[k];
         fz[k] = g02 * dx[k] + g12 * dy[k] + g22 * dz[k];
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_kernel(
   for (int f = 0; f < 7; ++f) {
     __syncthreads();
     for (int k = tid; k < Q3; k += blockDim.x)
-      sF[k] = (f == 0) ? alpha * WJ[e * Q3 + k] : Ge[(int64_t)gidx[f] * Q3 + k];
+      sF[k] = (f == 0) ? alpha * WJ[e * Q3 + k] : Ge[(int64_t)k * 6 + gidx[f]];
     __syncthreads();
     for (int r = 0; r < MAXN; ++r) {
       const int l = tid + r * DIAG_THREADS;
@@ -504,6 +504,10 @@ void launch_apply(const mfsem_op& op, const T* x, T* y, double alpha, bool stiff
                   hipStream_t s, bool accumulate) {
   if (!accumulate) zero<T>(y, op.d.n_dof * op.d.batch, s);
   if (op.d.n_elem == 0) return;
+  if (stiffness && launch_brick<T>(op, G_of<T>(op), WJ_of<T>(op),
+                                   op.use_det ? idet_of<T>(op) : nullptr, tables_of<T>(op), x, y,
+                                   (T)alpha, accumulate, s))
+    return;
   if (stiffness) dispatch<T, true>(op, x, y, (T)alpha, s);
   else dispatch<T, false>(op, x, y, (T)alpha, s);
 }

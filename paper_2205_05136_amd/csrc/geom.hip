@@ -34,7 +34,7 @@ struct GeomArgs {
   int oBm, oDm, ow;
   const double* sigma;    // [batch][n_elem][3] or null
   double s0, s1, s2;
-  double* G64;            // [batch][n_elem][6][Q^3] or null
+  double* G64;            // [batch][n_elem][Q^3][6] or null
   double* WJ64;           // [n_elem][Q^3] or null
   float* G32;
   float* WJ32;
@@ -172,10 +172,10 @@ __global__ __launch_bounds__(GEOM_THREADS) void geom_kernel(GeomArgs a) {
         const int r = ir[m], c = is[m];
         Gv[m] = wj * (T[r][0] * Ji[c][0] + T[r][1] * Ji[c][1] + T[r][2] * Ji[c][2]);
       }
-      const int64_t base = (((int64_t)bt * a.n_elem + e) * 6) * Q3 + k;
+      const int64_t base = (((int64_t)bt * a.n_elem + e) * Q3 + k) * 6;
       for (int m = 0; m < 6; ++m) {
-        if (a.G64) a.G64[base + (int64_t)m * Q3] = Gv[m];
-        if (a.G32) a.G32[base + (int64_t)m * Q3] = (float)Gv[m];
+        if (a.G64) a.G64[base + m] = Gv[m];
+        if (a.G32) a.G32[base + m] = (float)Gv[m];
       }
     }
   }
@@ -209,7 +209,7 @@ void run_geometry(mfsem_op& op, hipStream_t s) {
   a.idet32 = op.idet32;
   a.bad = op.bad;
   vfill<unsigned long long>(op.bad, 1, ~0ull, s);
-  vfill<unsigned long long>(op.bad + 1, 1, 0ull, s);
+  vfill<unsigned long long>(op.bad + 1, 2, 0ull, s);
   if (op.d.n_elem == 0) return;
   // one workgroup per element; the grid's x dimension holds up to 2^31-1
   geom_kernel<<<dim3((unsigned)op.d.n_elem), dim3(GEOM_THREADS), 0, s>>>(a);

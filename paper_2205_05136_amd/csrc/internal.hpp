@@ -83,6 +83,21 @@ __device__ inline void atomic_add(T* p, T v) {
   unsafeAtomicAdd(p, v);
 }
 
+// The six stored G entries of one quadrature point are contiguous
+// (G[batch][elem][point][6]), 16-byte aligned in FP64: three 16-byte loads
+// (three 8-byte loads in FP32) fetch a point, and the lanes of a wave that
+// walk consecutive points read one contiguous span.
+__device__ inline void load_g6(const double* p, double (&g)[6]) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+  const double2 a = q[0], b = q[1], c = q[2];
+  g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
+}
+__device__ inline void load_g6(const float* p, float (&g)[6]) {
+  const float2* q = reinterpret_cast<const float2*>(p);
+  const float2 a = q[0], b = q[1], c = q[2];
+  g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
+}
+
 }  // namespace mfsem
 
 // ------------------------------------------------------------ op object ---
@@ -92,7 +107,7 @@ struct mfsem_op {
   int64_t nq3;          // quadrature points per element
   double alpha;
   // device storage inside the caller's workspace
-  double* G64 = nullptr;   // [batch][n_elem][6][Q^3]
+  double* G64 = nullptr;   // [batch][n_elem][Q^3][6]
   double* WJ64 = nullptr;  // [n_elem][Q^3]
   float* G32 = nullptr;
   float* WJ32 = nullptr;
@@ -104,7 +119,11 @@ struct mfsem_op {
   double* idet64 = nullptr;  // [batch][n_elem]
   float* idet32 = nullptr;
   bool use_det = false;
-  // [0]: first failing (element, point) of the geometry; [1]: elements with det(sigma) <= 0
+  // structured lattice (elements per axis) when elem_dof follows the box numbering
+  bool structured = false;
+  int lat[3] = {0, 0, 0};
+  // [0]: first failing (element, point) of the geometry; [1]: elements with
+  // det(sigma) <= 0; [2]: element nodes that differ from the structured numbering
   unsigned long long* bad = nullptr;
   double* sigma_copy = nullptr;       // [batch][n_elem][3] (kept for set_sigma / grad)
   mfsem::TableOffsets off;
@@ -123,6 +142,11 @@ void launch_apply(const mfsem_op& op, const T* x, T* y, double alpha, bool stiff
                   hipStream_t s, bool accumulate = false);
 template <typename T>
 void launch_diag(const mfsem_op& op, T* d, hipStream_t s);
+// brick kernel on structured lattices (returns false when it does not apply)
+template <typename T>
+bool launch_brick(const mfsem_op& op, const T* G, const T* WJ, const T* idet, const T* tab,
+                  const T* x, T* y, T alpha, bool accumulate, hipStream_t s);
+void launch_lattice_check(const mfsem_op& op, unsigned long long* bad, hipStream_t s);
 void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, double* g,
                        hipStream_t s);
 
