@@ -91,14 +91,22 @@ __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
 
   T ur[P], us[P], ut[P];
   if (active) {
+    // this lane's rows of the 1D derivative matrix in registers; the
+    // lane-uniform entries of the third direction from scalar loads
+    T dx[P], dy[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      dx[m] = sD[ia * P + m];
+      dy[m] = sD[ib * P + m];
+    }
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       T r = 0, s = 0, t = 0;
 #pragma unroll
       for (int m = 0; m < P; ++m) {
-        r += sD[ia * P + m] * su[c * P2 + ib * P + m];
-        s += sD[ib * P + m] * su[c * P2 + m * P + ia];
-        t += sD[c * P + m] * u[m];
+        r += dx[m] * su[c * P2 + ib * P + m];
+        s += dy[m] * su[c * P2 + m * P + ia];
+        t += Dtab[c * P + m] * u[m];
       }
       ur[c] = r;
       us[c] = s;
@@ -138,14 +146,20 @@ __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
   __syncthreads();
 
   if (active) {
+    T dxt[P], dyt[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      dxt[m] = sD[m * P + ia];
+      dyt[m] = sD[m * P + ib];
+    }
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       T v = out[c];
 #pragma unroll
       for (int m = 0; m < P; ++m) {
-        v += sD[m * P + ia] * su[c * P2 + ib * P + m];
-        v += sD[m * P + ib] * sv[c * P2 + m * P + ia];
-        v += sD[m * P + c] * ft[m];
+        v += dxt[m] * su[c * P2 + ib * P + m];
+        v += dyt[m] * sv[c * P2 + m * P + ia];
+        v += Dtab[m * P + c] * ft[m];
       }
       atomic_add(&y[gi[c]], v);
     }

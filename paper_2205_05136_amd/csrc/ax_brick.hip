@@ -129,6 +129,14 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS, BrickCfg<P>::WAVES) void ax_b
 #pragma unroll
     for (int c = 0; c < P; ++c) u[c] = xs[o + LX * LY * c];
     const T wab = sw[ia] * sw[ib];
+    // this lane's rows of the 1D derivative matrix stay in registers; the
+    // lane-uniform entries of the third direction come from scalar loads
+    T dx[P], dy[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      dx[m] = sD[ia * P + m];
+      dy[m] = sD[ib * P + m];
+    }
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       const T g00 = g[c][0], g01 = g[c][1], g02 = g[c][2];
@@ -136,9 +144,9 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS, BrickCfg<P>::WAVES) void ax_b
       T r = 0, s = 0, t = 0;
 #pragma unroll
       for (int m = 0; m < P; ++m) {
-        r += sD[ia * P + m] * xs[o - ia + m + LX * LY * c];
-        s += sD[ib * P + m] * xs[o - LX * ib + LX * m + LX * LY * c];
-        t += sD[c * P + m] * u[m];
+        r += dx[m] * xs[o - ia + m + LX * LY * c];
+        s += dy[m] * xs[o - LX * ib + LX * m + LX * LY * c];
+        t += Dtab[c * P + m] * u[m];
       }
       const int q = c * P2 + ab;
       Fe[q] = g00 * r + g01 * s + g02 * t;
@@ -159,14 +167,20 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS, BrickCfg<P>::WAVES) void ax_b
   __syncthreads();
   // 4. transposed passes, summed into the LDS lattice
   if (active) {
+    T dxt[P], dyt[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      dxt[m] = sD[m * P + ia];
+      dyt[m] = sD[m * P + ib];
+    }
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       T v = out[c];
 #pragma unroll
       for (int m = 0; m < P; ++m) {
-        v += sD[m * P + ia] * Fe[c * P2 + ib * P + m];
-        v += sD[m * P + ib] * Fe[P3 + c * P2 + m * P + ia];
-        v += sD[m * P + c] * ft[m];
+        v += dxt[m] * Fe[c * P2 + ib * P + m];
+        v += dyt[m] * Fe[P3 + c * P2 + m * P + ia];
+        v += Dtab[m * P + c] * ft[m];
       }
       lds_add(&ys[o + LX * LY * c], v);
     }
