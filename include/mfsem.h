@@ -229,8 +229,9 @@ mfsem_status mfsem_mg_create(const mfsem_mg_desc* d, void* ws, size_t ws_bytes, 
 mfsem_status mfsem_mg_destroy(mfsem_mg* mg);
 
 /* z = V(r): one V-cycle from a zero guess.  r, z [device][batch][n_dof] in
- * the cycle's precision.  Uses buffers inside the workspace: calls on the
- * same mg must not overlap.                                                 */
+ * the cycle's precision.  Uses buffers inside the workspace, which hold
+ * zeros between cycles (each kernel clears what it read last): calls on the
+ * same mg must not overlap, and r and z must not alias.                     */
 mfsem_status mfsem_mg_vcycle(const mfsem_mg* mg, const void* r, void* z, void* stream);
 
 /* lambda_max per level and batch member, [host] [n_levels][batch]. */

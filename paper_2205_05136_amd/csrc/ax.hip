@@ -520,7 +520,7 @@ void launch_apply(const mfsem_op& op, const T* x, T* y, double alpha, bool stiff
   if (op.d.n_elem == 0) return;
   if (stiffness && launch_brick<T>(op, G_of<T>(op), WJ_of<T>(op),
                                    op.use_det ? idet_of<T>(op) : nullptr, tables_of<T>(op), x, y,
-                                   (T)alpha, accumulate, s))
+                                   (T)alpha, s))
     return;
   if (stiffness) dispatch<T, true>(op, x, y, (T)alpha, s);
   else dispatch<T, false>(op, x, y, (T)alpha, s);

@@ -58,7 +58,7 @@ template <typename T, int P>
 __global__ __launch_bounds__(BrickCfg<P>::THREADS, BrickCfg<P>::WAVES) void ax_brick_kernel(
     int nx, int ny, int nz, int64_t n_dof, const T* __restrict__ G, const T* __restrict__ WJ,
     const T* __restrict__ idet, T alpha, const T* __restrict__ Dtab, const T* __restrict__ wtab,
-    const T* __restrict__ x, T* __restrict__ y, int accumulate) {
+    const T* __restrict__ x, T* __restrict__ y) {
   using C = BrickCfg<P>;
   constexpr int p = C::p, P2 = C::P2, P3 = C::P3, NE = C::NE;
   constexpr int BX = C::BX, BY = C::BY, BZ = C::BZ, LX = C::LX, LY = C::LY, LN = C::LN;
@@ -186,34 +186,26 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS, BrickCfg<P>::WAVES) void ax_b
     }
   }
   __syncthreads();
-  // 5. write back: plain stores for nodes only this brick touches
-  const bool first_x = ex0 == 0, last_x = ex0 + nex == nx;
-  const bool first_y = ey0 == 0, last_y = ey0 + ney == ny;
-  const bool first_z = ez0 == 0, last_z = ez0 + nez == nz;
+  // 5. write back: every lattice node of the brick is added to y through the L2
+  // atomic unit (y holds zero or the sum being accumulated into).  Plain stores
+  // of the nodes no other brick touches, interleaved on the same cache lines
+  // with other bricks' atomic adds, measured slower than atomics for all nodes.
   for (int n = tid; n < LN; n += blockDim.x) {
     const int i = n % LX, j = (n / LX) % LY, k = n / (LX * LY);
     if (i > nex * p || j > ney * p || k > nez * p) continue;
-    const bool own = (i > 0 || first_x) && (i < nex * p || last_x) && (j > 0 || first_y) &&
-                     (j < ney * p || last_y) && (k > 0 || first_z) && (k < nez * p || last_z);
-    T* dst = y + (I0 + i) + NX * ((J0 + j) + NY * (K0 + k));
-    // Every node goes through the L2 atomic unit: plain stores of the nodes this
-    // brick owns, interleaved on the same cache lines with other bricks' atomic
-    // adds, measured slower than atomics for all nodes.
-    (void)own;
-    atomic_add(dst, ys[n]);
+    atomic_add(y + (I0 + i) + NX * ((J0 + j) + NY * (K0 + k)), ys[n]);
   }
 }
 
 template <typename T, int P>
 void run(const mfsem_op& op, const T* G, const T* WJ, const T* idet, const T* tab, const T* x,
-         T* y, T alpha, bool accumulate, hipStream_t s) {
+         T* y, T alpha, hipStream_t s) {
   using C = BrickCfg<P>;
   const int nx = op.lat[0], ny = op.lat[1], nz = op.lat[2];
   const int64_t nb = (int64_t)((nx + C::BX - 1) / C::BX) * ((ny + C::BY - 1) / C::BY) *
                      ((nz + C::BZ - 1) / C::BZ);
   ax_brick_kernel<T, P><<<dim3((unsigned)nb, op.d.batch), dim3(C::THREADS), 0, s>>>(
-      nx, ny, nz, op.d.n_dof, G, WJ, idet, alpha, tab + op.off.Db, tab + op.off.w, x, y,
-      accumulate ? 1 : 0);
+      nx, ny, nz, op.d.n_dof, G, WJ, idet, alpha, tab + op.off.Db, tab + op.off.w, x, y);
   MFSEM_LAUNCH("ax_brick_kernel");
 }
 
@@ -221,26 +213,25 @@ void run(const mfsem_op& op, const T* G, const T* WJ, const T* idet, const T* ta
 
 template <typename T>
 bool launch_brick(const mfsem_op& op, const T* G, const T* WJ, const T* idet, const T* tab,
-                  const T* x, T* y, T alpha, bool accumulate, hipStream_t s) {
+                  const T* x, T* y, T alpha, hipStream_t s) {
   if (!op.structured || op.d.quad != MFSEM_GLL || op.d.n_elem == 0) return false;
   switch (op.P) {
-    case 2: run<T, 2>(op, G, WJ, idet, tab, x, y, alpha, accumulate, s); return true;
-    case 3: run<T, 3>(op, G, WJ, idet, tab, x, y, alpha, accumulate, s); return true;
-    case 4: run<T, 4>(op, G, WJ, idet, tab, x, y, alpha, accumulate, s); return true;
-    case 5: run<T, 5>(op, G, WJ, idet, tab, x, y, alpha, accumulate, s); return true;
-    case 6: run<T, 6>(op, G, WJ, idet, tab, x, y, alpha, accumulate, s); return true;
-    case 7: run<T, 7>(op, G, WJ, idet, tab, x, y, alpha, accumulate, s); return true;
-    case 8: run<T, 8>(op, G, WJ, idet, tab, x, y, alpha, accumulate, s); return true;
-    case 9: run<T, 9>(op, G, WJ, idet, tab, x, y, alpha, accumulate, s); return true;
+    case 2: run<T, 2>(op, G, WJ, idet, tab, x, y, alpha, s); return true;
+    case 3: run<T, 3>(op, G, WJ, idet, tab, x, y, alpha, s); return true;
+    case 4: run<T, 4>(op, G, WJ, idet, tab, x, y, alpha, s); return true;
+    case 5: run<T, 5>(op, G, WJ, idet, tab, x, y, alpha, s); return true;
+    case 6: run<T, 6>(op, G, WJ, idet, tab, x, y, alpha, s); return true;
+    case 7: run<T, 7>(op, G, WJ, idet, tab, x, y, alpha, s); return true;
+    case 8: run<T, 8>(op, G, WJ, idet, tab, x, y, alpha, s); return true;
+    case 9: run<T, 9>(op, G, WJ, idet, tab, x, y, alpha, s); return true;
   }
   return false;
 }
 
 template bool launch_brick<double>(const mfsem_op&, const double*, const double*, const double*,
-                                   const double*, const double*, double*, double, bool,
-                                   hipStream_t);
+                                   const double*, const double*, double*, double, hipStream_t);
 template bool launch_brick<float>(const mfsem_op&, const float*, const float*, const float*,
-                                  const float*, const float*, float*, float, bool, hipStream_t);
+                                  const float*, const float*, float*, float, hipStream_t);
 
 // ------------------------------------------------ structured-map check -------
 namespace {

@@ -137,15 +137,18 @@ namespace mfsem {
 void op_layout(mfsem_op& op, Arena& a);
 void run_geometry(mfsem_op& op, hipStream_t s);  // fills G/WJ and the bad flag
 
+// y = A x, or y += A x with accumulate (the kernels add into y; without
+// accumulate y is cleared first)
 template <typename T>
 void launch_apply(const mfsem_op& op, const T* x, T* y, double alpha, bool stiffness,
                   hipStream_t s, bool accumulate = false);
 template <typename T>
 void launch_diag(const mfsem_op& op, T* d, hipStream_t s);
-// brick kernel on structured lattices (returns false when it does not apply)
+// brick kernel on structured lattices, adding into y (returns false when it
+// does not apply)
 template <typename T>
 bool launch_brick(const mfsem_op& op, const T* G, const T* WJ, const T* idet, const T* tab,
-                  const T* x, T* y, T alpha, bool accumulate, hipStream_t s);
+                  const T* x, T* y, T alpha, hipStream_t s);
 void launch_lattice_check(const mfsem_op& op, unsigned long long* bad, hipStream_t s);
 void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, double* g,
                        hipStream_t s);

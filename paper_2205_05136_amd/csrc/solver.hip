@@ -176,43 +176,52 @@ TransferArgs<T> transfer_args(const mfsem_mg& mg, int l) {
   return a;
 }
 
+// Chebyshev smoothing; the level's t is zero on entry and on exit (every
+// product with A adds into it and the Chebyshev step clears it after reading).
+// With clear_b the last step also clears b.
 template <typename T>
-void smooth(const mfsem_mg& mg, const mfsem_mg_level& L, const T* b, T* x, bool from_zero,
-            hipStream_t s) {
+void smooth(const mfsem_mg& mg, const mfsem_mg_level& L, T* b, T* x, bool from_zero,
+            bool clear_b, hipStream_t s) {
   const int B = mg.batch;
   T* t = P_<T>(L.t);
   T* d = P_<T>(L.d);
   const T* dinv = P_<T>(L.dinv);
   for (int j = 0; j < L.steps; ++j) {
     const double* c = L.coef + (size_t)j * B * 2;
+    const bool last = j + 1 == L.steps;
     if (j == 0 && from_zero) {
-      vcheb<T>(x, d, b, nullptr, dinv, L.n, B, c, true, s);
+      vcheb<T>(x, d, b, nullptr, dinv, L.n, B, c, true, false, clear_b && last, s);
     } else {
-      launch_apply<T>(*L.op, x, t, L.op->alpha, true, s);
-      vcheb<T>(x, d, b, t, dinv, L.n, B, c, false, s);
+      launch_apply<T>(*L.op, x, t, L.op->alpha, true, s, true);
+      vcheb<T>(x, d, b, t, dinv, L.n, B, c, false, true, clear_b && last, s);
     }
   }
 }
 
+// V-cycle from x = 0.  Zero-on-consume invariant: between V-cycles every
+// level's t, and the b of every level below the finest, hold zeros, so products
+// with A and the restriction add into them without clearing launches; each
+// buffer is cleared by the kernel that reads it last.  b of the finest level is
+// the caller's and is never written.
 template <typename T>
-void vcycle(const mfsem_mg& mg, int l, const T* b, T* x, hipStream_t s) {
+void vcycle(const mfsem_mg& mg, int l, T* b, T* x, hipStream_t s) {
   const mfsem_mg_level& L = mg.lv[l];
   const int B = mg.batch;
+  const bool own_b = l > 0;
   if (l + 1 == (int)mg.lv.size()) {
-    smooth<T>(mg, L, b, x, true, s);
+    smooth<T>(mg, L, b, x, true, own_b, s);
     return;
   }
   const mfsem_mg_level& C = mg.lv[l + 1];
-  smooth<T>(mg, L, b, x, true, s);
+  smooth<T>(mg, L, b, x, true, false, s);
   T* t = P_<T>(L.t);
-  launch_apply<T>(*L.op, x, t, L.op->alpha, true, s);
+  launch_apply<T>(*L.op, x, t, L.op->alpha, true, s, true);
   const TransferArgs<T> ta = transfer_args<T>(mg, l);
-  vfill<T>(P_<T>(C.b), C.n * B, T(0), s);
   launch_restrict<T>(ta, B, b, t, P_<T>(L.wmult), P_<T>(C.b), s);
   vcycle<T>(mg, l + 1, P_<T>(C.b), P_<T>(C.x), s);
-  launch_prolong<T>(ta, B, P_<T>(C.x), t, s);
-  vaxpy<T>(x, t, L.n * B, s);
-  smooth<T>(mg, L, b, x, false, s);
+  launch_prolong<T>(ta, B, P_<T>(C.x), t, s);  // overwrites t
+  vaxpy<T>(x, t, L.n * B, true, s);
+  smooth<T>(mg, L, b, x, false, own_b, s);
 }
 
 }  // namespace
@@ -285,6 +294,20 @@ void mg_setup(mfsem_mg& mg, hipStream_t s) {
     cheb_coefficients(mg, L, c);
     MFSEM_HIP(hipMemcpy(L.coef, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice));
   }
+  // establish the V-cycle's zero-on-consume invariant (the eigenvalue
+  // estimate used these buffers as scratch)
+  for (size_t l = 0; l < mg.lv.size(); ++l) {
+    mfsem_mg_level& L = mg.lv[l];
+    const int64_t nb = L.n * B;
+    if (f64) {
+      vfill<double>(P_<double>(L.t), nb, 0.0, s);
+      if (l > 0) vfill<double>(P_<double>(L.b), nb, 0.0, s);
+    } else {
+      vfill<float>(P_<float>(L.t), nb, 0.0f, s);
+      if (l > 0) vfill<float>(P_<float>(L.b), nb, 0.0f, s);
+    }
+  }
+  MFSEM_HIP(hipStreamSynchronize(s));
 }
 
 template <typename T>
@@ -307,8 +330,10 @@ void mg_transfer(const mfsem_mg& mg, int level, int direction, const void* in, v
 }
 
 void mg_vcycle(const mfsem_mg& mg, const void* r, void* z, hipStream_t s) {
-  if (mg.prec == MFSEM_F64) vcycle<double>(mg, 0, static_cast<const double*>(r), static_cast<double*>(z), s);
-  else vcycle<float>(mg, 0, static_cast<const float*>(r), static_cast<float*>(z), s);
+  // r is only read: the finest level never clears its b
+  void* b = const_cast<void*>(r);
+  if (mg.prec == MFSEM_F64) vcycle<double>(mg, 0, static_cast<double*>(b), static_cast<double*>(z), s);
+  else vcycle<float>(mg, 0, static_cast<float*>(b), static_cast<float*>(z), s);
 }
 
 // ------------------------------------------------------------------ PCG ---
@@ -383,10 +408,10 @@ mfsem_status pcg_solve(const mfsem_op& op, const mfsem_mg* mg, const double* b, 
     MFSEM_HIP(hipStreamSynchronize(s));
   };
 
-  // r = b - A x
+  // r = b - A x; q is left at zero, and every later q = A p adds into it
+  // (the update of x and r clears it again)
   launch_apply<double>(op, x, w.q, op.alpha, true, s);
-  vresidual(b, w.q, w.r, n, B, w.partial, w.red, s);
-  pcg_scalars(w.sc, w.red, B, PCG_SET_RR_BB, s);
+  vresidual(b, w.q, w.r, n, B, w.partial, w.red, true, w.sc, s);
   fetch();
   std::vector<double> tol(B);
   std::vector<char> done(B, 0);
@@ -410,16 +435,14 @@ mfsem_status pcg_solve(const mfsem_op& op, const mfsem_mg* mg, const double* b, 
 
   for (int it = 1; live > 0 && it <= o.max_it; ++it) {
     precondition();
-    vdot2<double>(w.r, w.z, o.flexible ? w.zo : nullptr, n, B, w.partial, w.red, s);
-    pcg_scalars(w.sc, w.red, B, it == 1 ? PCG_SET_RZ_FIRST : PCG_SET_RZ, s);
+    vdot2<double>(w.r, w.z, o.flexible ? w.zo : nullptr, n, B, w.partial, w.red, s, w.sc,
+                  it == 1 ? PCG_SET_RZ_FIRST : PCG_SET_RZ);
     if (o.flexible)
       MFSEM_HIP(hipMemcpyAsync(w.zo, w.z, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
     vp(w.p, w.z, n, B, w.sc, s);
-    launch_apply<double>(op, w.p, w.q, op.alpha, true, s);
-    vdot2<double>(w.p, w.q, nullptr, n, B, w.partial, w.red, s);
-    pcg_scalars(w.sc, w.red, B, PCG_SET_PQ, s);
+    launch_apply<double>(op, w.p, w.q, op.alpha, true, s, true);
+    vdot2<double>(w.p, w.q, nullptr, n, B, w.partial, w.red, s, w.sc, PCG_SET_PQ);
     vxr(x, w.r, w.p, w.q, n, B, w.sc, w.partial, w.red, s);
-    pcg_scalars(w.sc, w.red, B, PCG_SET_RR, s);
     fetch();
     changed = false;
     live = 0;

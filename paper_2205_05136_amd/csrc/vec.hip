@@ -62,24 +62,69 @@ __global__ __launch_bounds__(VT) void dot2_kernel(const T* __restrict__ a, const
   }
 }
 
-// out[bt*2 + j] = sum of the partials of member bt
+// Per-member scalar updates of (P)CG from the two reduced values of a dot.
+__device__ void pcg_update(PcgScalars& s, double v0, double v1, int what) {
+  switch (what) {
+    case PCG_SET_RR_BB:  // after residual_kernel
+      s.rr = v0;
+      s.bb = v1;
+      break;
+    case PCG_SET_PQ:  // after dot(p, q)
+      s.pq = v0;
+      if (s.active && !(v0 > 0.0)) {
+        s.active = 0;
+        s.flag = (v0 == v0) ? MFSEM_EBREAKDOWN : MFSEM_ENONFINITE;
+      }
+      s.alpha = s.rz / v0;
+      break;
+    case PCG_SET_RR:  // after xr_kernel
+      if (s.active) s.rr = v0;
+      break;
+    case PCG_SET_RZ_FIRST:  // after dot(r, z) on the first iteration
+      s.rz = v0;
+      s.beta = 0.0;
+      if (s.active && !(v0 > 0.0)) {
+        s.active = 0;
+        s.flag = (v0 == v0) ? MFSEM_EBREAKDOWN : MFSEM_ENONFINITE;
+      }
+      break;
+    case PCG_SET_RZ:  // dot(r, z) and dot(r, z_old): beta (flexible uses v0 - v1)
+      if (s.active) {
+        const double num = s.flexible ? v0 - v1 : v0;
+        s.beta = num / s.rz;
+        s.rz = v0;
+        if (!(v0 > 0.0)) {
+          s.active = 0;
+          s.flag = (v0 == v0) ? MFSEM_EBREAKDOWN : MFSEM_ENONFINITE;
+        }
+      }
+      break;
+  }
+}
+
+// out[bt*2 + j] = sum of the partials of member bt; with sc, also the (P)CG
+// scalar update `what` of member bt (saves a launch per dot product)
 __global__ __launch_bounds__(VT) void reduce_kernel(const double* __restrict__ partial, int nblk,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, PcgScalars* sc,
+                                                    int what) {
   __shared__ double sh[VT / 64];
   const int bt = blockIdx.x;
+  double v[2];
   for (int j = 0; j < 2; ++j) {
     double s = 0;
     for (int i = threadIdx.x; i < nblk; i += VT) s += partial[((int64_t)bt * nblk + i) * 2 + j];
     s = block_sum(s, sh);
+    v[j] = s;
     if (threadIdx.x == 0) out[bt * 2 + j] = s;
   }
+  if (sc && threadIdx.x == 0) pcg_update(sc[bt], v[0], v[1], what);
 }
 
-// r = b - q ; partial sums of r.r and b.b
+// r = b - q ; partial sums of r.r and b.b; q is cleared after use (zero_q)
 __global__ __launch_bounds__(VT) void residual_kernel(const double* __restrict__ b,
-                                                      const double* __restrict__ q,
+                                                      double* __restrict__ q,
                                                       double* __restrict__ r, int64_t n,
-                                                      double* __restrict__ partial) {
+                                                      double* __restrict__ partial, int zero_q) {
   __shared__ double sh[VT / 64];
   const int bt = blockIdx.y;
   const int64_t off = (int64_t)bt * n;
@@ -87,6 +132,7 @@ __global__ __launch_bounds__(VT) void residual_kernel(const double* __restrict__
   for (int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
     const double bv = b[off + i];
     const double rv = q ? bv - q[off + i] : bv;
+    if (q && zero_q) q[off + i] = 0.0;
     r[off + i] = rv;
     s0 += rv * rv;
     s1 += bv * bv;
@@ -100,10 +146,11 @@ __global__ __launch_bounds__(VT) void residual_kernel(const double* __restrict__
   }
 }
 
-// alpha = rz/pq (0 for finished members); x += alpha p ; r -= alpha q ; partial r.r
+// alpha = rz/pq; x += alpha p ; r -= alpha q ; partial r.r (finished members
+// are left as they are); q is cleared for the next q = A p, which accumulates
 __global__ __launch_bounds__(VT) void xr_kernel(double* __restrict__ x, double* __restrict__ r,
                                                 const double* __restrict__ p,
-                                                const double* __restrict__ q, int64_t n,
+                                                double* __restrict__ q, int64_t n,
                                                 const PcgScalars* __restrict__ sc,
                                                 double* __restrict__ partial) {
   __shared__ double sh[VT / 64];
@@ -112,12 +159,14 @@ __global__ __launch_bounds__(VT) void xr_kernel(double* __restrict__ x, double* 
   const bool act = sc[bt].active != 0;
   const double al = sc[bt].alpha;
   double s0 = 0;
-  for (int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x; act && i < n;
-       i += (int64_t)gridDim.x * VT) {
-    x[off + i] += al * p[off + i];
-    const double rv = r[off + i] - al * q[off + i];
-    r[off + i] = rv;
-    s0 += rv * rv;
+  for (int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+    if (act) {
+      x[off + i] += al * p[off + i];
+      const double rv = r[off + i] - al * q[off + i];
+      r[off + i] = rv;
+      s0 += rv * rv;
+    }
+    q[off + i] = 0.0;
   }
   s0 = block_sum(s0, sh);
   if (threadIdx.x == 0) {
@@ -138,27 +187,36 @@ __global__ __launch_bounds__(VT) void p_kernel(double* __restrict__ p, const dou
     p[off + i] = (be != 0.0) ? z[off + i] + be * p[off + i] : z[off + i];
 }
 
-// Chebyshev step: d = c1*d + c2*dinv*(b - t); x = (overwrite ? d : x + d)
+// Chebyshev step: d = c1*d + c2*dinv*(b - t); x = (overwrite ? d : x + d).
+// flags: 1 = overwrite x, 2 = clear t after use (the next A x accumulates into
+// it), 4 = clear b after use (its last read in this V-cycle)
 template <typename T>
 __global__ __launch_bounds__(VT) void cheb_kernel(T* __restrict__ x, T* __restrict__ d,
-                                                  const T* __restrict__ b, const T* __restrict__ t,
+                                                  T* __restrict__ b, T* __restrict__ t,
                                                   const T* __restrict__ dinv, int64_t n,
-                                                  const double* __restrict__ coef, int overwrite) {
+                                                  const double* __restrict__ coef, int flags) {
   const int bt = blockIdx.y;
   const int64_t off = (int64_t)bt * n;
   const T c1 = (T)coef[bt * 2], c2 = (T)coef[bt * 2 + 1];
   for (int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
-    const T r = t ? b[off + i] - t[off + i] : b[off + i];
+    const T bv = b[off + i];
+    const T r = t ? bv - t[off + i] : bv;
     const T dv = (c1 != T(0) ? c1 * d[off + i] : T(0)) + c2 * dinv[off + i] * r;
     d[off + i] = dv;
-    x[off + i] = overwrite ? dv : x[off + i] + dv;
+    x[off + i] = (flags & 1) ? dv : x[off + i] + dv;
+    if (t && (flags & 2)) t[off + i] = T(0);
+    if (flags & 4) b[off + i] = T(0);
   }
 }
 
+// y += x, then x = 0 when clear_x
 template <typename T>
-__global__ void axpy_kernel(T* __restrict__ y, const T* __restrict__ x, int64_t n) {
+__global__ void axpy_kernel(T* __restrict__ y, T* __restrict__ x, int64_t n, int clear_x) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] += x[i];
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    y[i] += x[i];
+    if (clear_x) x[i] = T(0);
+  }
 }
 
 template <typename T>
@@ -198,41 +256,6 @@ __global__ void random_kernel(double* __restrict__ x, int64_t n, uint64_t seed) 
   }
 }
 
-// Per-member scalar updates of (P)CG, one thread per member.
-__global__ void pcg_scalar_kernel(PcgScalars* sc, const double* red, int batch, int what) {
-  const int bt = blockIdx.x * blockDim.x + threadIdx.x;
-  if (bt >= batch) return;
-  PcgScalars& s = sc[bt];
-  const double v0 = red[bt * 2], v1 = red[bt * 2 + 1];
-  switch (what) {
-    case PCG_SET_RR_BB:  // after residual_kernel
-      s.rr = v0;
-      s.bb = v1;
-      break;
-    case PCG_SET_PQ:  // after dot(p, q)
-      s.pq = v0;
-      if (s.active && !(v0 > 0.0)) { s.active = 0; s.flag = (v0 == v0) ? MFSEM_EBREAKDOWN : MFSEM_ENONFINITE; }
-      s.alpha = s.rz / v0;
-      break;
-    case PCG_SET_RR:  // after xr_kernel
-      if (s.active) s.rr = v0;
-      break;
-    case PCG_SET_RZ_FIRST:  // after dot(r, z) on the first iteration
-      s.rz = v0;
-      s.beta = 0.0;
-      if (s.active && !(v0 > 0.0)) { s.active = 0; s.flag = (v0 == v0) ? MFSEM_EBREAKDOWN : MFSEM_ENONFINITE; }
-      break;
-    case PCG_SET_RZ:  // dot(r, z) and dot(r, z_old): beta (flexible uses v0 - v1)
-      if (s.active) {
-        const double num = s.flexible ? v0 - v1 : v0;
-        s.beta = num / s.rz;
-        s.rz = v0;
-        if (!(v0 > 0.0)) { s.active = 0; s.flag = (v0 == v0) ? MFSEM_EBREAKDOWN : MFSEM_ENONFINITE; }
-      }
-      break;
-  }
-}
-
 unsigned grid_for(int64_t n) {
   int64_t b = (n + VT - 1) / VT;
   if (b > 1024) b = 1024;
@@ -260,29 +283,29 @@ void vcast(const A* x, B* y, int64_t n, hipStream_t s) {
 
 template <typename T>
 void vdot2(const T* a, const T* b, const T* c, int64_t n, int batch, double* partial,
-           double* out, hipStream_t s) {
+           double* out, hipStream_t s, PcgScalars* sc, int what) {
   const unsigned nb = grid_for(n);
   dot2_kernel<T><<<dim3(nb, batch), VT, 0, s>>>(a, b, c, n, partial);
   MFSEM_LAUNCH("dot2_kernel");
-  reduce_kernel<<<batch, VT, 0, s>>>(partial, (int)nb, out);
+  reduce_kernel<<<batch, VT, 0, s>>>(partial, (int)nb, out, sc, what);
   MFSEM_LAUNCH("reduce_kernel");
 }
 
-void vresidual(const double* b, const double* q, double* r, int64_t n, int batch, double* partial,
-               double* out, hipStream_t s) {
+void vresidual(const double* b, double* q, double* r, int64_t n, int batch, double* partial,
+               double* out, bool zero_q, PcgScalars* sc, hipStream_t s) {
   const unsigned nb = grid_for(n);
-  residual_kernel<<<dim3(nb, batch), VT, 0, s>>>(b, q, r, n, partial);
+  residual_kernel<<<dim3(nb, batch), VT, 0, s>>>(b, q, r, n, partial, zero_q ? 1 : 0);
   MFSEM_LAUNCH("residual_kernel");
-  reduce_kernel<<<batch, VT, 0, s>>>(partial, (int)nb, out);
+  reduce_kernel<<<batch, VT, 0, s>>>(partial, (int)nb, out, sc, PCG_SET_RR_BB);
   MFSEM_LAUNCH("reduce_kernel");
 }
 
-void vxr(double* x, double* r, const double* p, const double* q, int64_t n, int batch,
-         const PcgScalars* sc, double* partial, double* out, hipStream_t s) {
+void vxr(double* x, double* r, const double* p, double* q, int64_t n, int batch,
+         PcgScalars* sc, double* partial, double* out, hipStream_t s) {
   const unsigned nb = grid_for(n);
   xr_kernel<<<dim3(nb, batch), VT, 0, s>>>(x, r, p, q, n, sc, partial);
   MFSEM_LAUNCH("xr_kernel");
-  reduce_kernel<<<batch, VT, 0, s>>>(partial, (int)nb, out);
+  reduce_kernel<<<batch, VT, 0, s>>>(partial, (int)nb, out, sc, PCG_SET_RR);
   MFSEM_LAUNCH("reduce_kernel");
 }
 
@@ -291,22 +314,18 @@ void vp(double* p, const double* z, int64_t n, int batch, const PcgScalars* sc, 
   MFSEM_LAUNCH("p_kernel");
 }
 
-void pcg_scalars(PcgScalars* sc, const double* red, int batch, int what, hipStream_t s) {
-  pcg_scalar_kernel<<<(batch + 63) / 64, 64, 0, s>>>(sc, red, batch, what);
-  MFSEM_LAUNCH("pcg_scalar_kernel");
-}
-
 template <typename T>
-void vcheb(T* x, T* d, const T* b, const T* t, const T* dinv, int64_t n, int batch,
-           const double* coef, bool overwrite, hipStream_t s) {
-  cheb_kernel<T><<<dim3(grid_for(n), batch), VT, 0, s>>>(x, d, b, t, dinv, n, coef, overwrite ? 1 : 0);
+void vcheb(T* x, T* d, T* b, T* t, const T* dinv, int64_t n, int batch, const double* coef,
+           bool overwrite, bool clear_t, bool clear_b, hipStream_t s) {
+  const int flags = (overwrite ? 1 : 0) | (clear_t ? 2 : 0) | (clear_b ? 4 : 0);
+  cheb_kernel<T><<<dim3(grid_for(n), batch), VT, 0, s>>>(x, d, b, t, dinv, n, coef, flags);
   MFSEM_LAUNCH("cheb_kernel");
 }
 
 template <typename T>
-void vaxpy(T* y, const T* x, int64_t n, hipStream_t s) {
+void vaxpy(T* y, T* x, int64_t n, bool clear_x, hipStream_t s) {
   if (n <= 0) return;
-  axpy_kernel<T><<<grid_for(n), VT, 0, s>>>(y, x, n);
+  axpy_kernel<T><<<grid_for(n), VT, 0, s>>>(y, x, n, clear_x ? 1 : 0);
   MFSEM_LAUNCH("axpy_kernel");
 }
 
@@ -338,10 +357,10 @@ void vrandom(double* x, int64_t n, uint64_t seed, hipStream_t s) {
 #define MFSEM_INST(T)                                                                        \
   template void vfill<T>(T*, int64_t, T, hipStream_t);                                       \
   template void vdot2<T>(const T*, const T*, const T*, int64_t, int, double*, double*,       \
-                         hipStream_t);                                                       \
-  template void vcheb<T>(T*, T*, const T*, const T*, const T*, int64_t, int, const double*, \
+                         hipStream_t, PcgScalars*, int);                                     \
+  template void vcheb<T>(T*, T*, T*, T*, const T*, int64_t, int, const double*, bool, bool,  \
                          bool, hipStream_t);                                                 \
-  template void vaxpy<T>(T*, const T*, int64_t, hipStream_t);                                \
+  template void vaxpy<T>(T*, T*, int64_t, bool, hipStream_t);                                \
   template void vinvert<T>(T*, int64_t, hipStream_t);                                       \
   template void vlin<T>(T*, const T*, int64_t, int, const double*, hipStream_t);              \
   template void vmul<T>(T*, const T*, const T*, int64_t, int, hipStream_t);

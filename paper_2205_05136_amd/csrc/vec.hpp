@@ -15,25 +15,29 @@ enum { PCG_SET_RR_BB = 0, PCG_SET_PQ = 1, PCG_SET_RR = 2, PCG_SET_RZ_FIRST = 3, 
 
 int dot_blocks(int64_t n);  // partial-sum blocks per member for vectors of length n
 
-// out[bt*2 + {0,1}] = (a.b, a.c) per member (c may be null -> 0)
+// out[bt*2 + {0,1}] = (a.b, a.c) per member (c may be null -> 0); with sc,
+// the reduction also applies the scalar update `what` to each member
 template <typename T>
 void vdot2(const T* a, const T* b, const T* c, int64_t n, int batch, double* partial,
-           double* out, hipStream_t s);
-// r = b - q (q may be null), out = (r.r, b.b)
-void vresidual(const double* b, const double* q, double* r, int64_t n, int batch,
-               double* partial, double* out, hipStream_t s);
-// x += alpha p, r -= alpha q with alpha from sc; out[bt*2] = r.r
-void vxr(double* x, double* r, const double* p, const double* q, int64_t n, int batch,
-         const PcgScalars* sc, double* partial, double* out, hipStream_t s);
+           double* out, hipStream_t s, PcgScalars* sc = nullptr, int what = 0);
+// r = b - q (q may be null; cleared afterwards when zero_q), out = (r.r, b.b),
+// then sc[bt].{rr, bb} = out when sc is given
+void vresidual(const double* b, double* q, double* r, int64_t n, int batch, double* partial,
+               double* out, bool zero_q, PcgScalars* sc, hipStream_t s);
+// x += alpha p, r -= alpha q with alpha from sc; q = 0; out[bt*2] = r.r and
+// sc[bt].rr is updated for active members
+void vxr(double* x, double* r, const double* p, double* q, int64_t n, int batch,
+         PcgScalars* sc, double* partial, double* out, hipStream_t s);
 // p = z + beta p (p = z when beta == 0)
 void vp(double* p, const double* z, int64_t n, int batch, const PcgScalars* sc, hipStream_t s);
-void pcg_scalars(PcgScalars* sc, const double* red, int batch, int what, hipStream_t s);
-// d = c1 d + c2 dinv (b - t); x = overwrite ? d : x + d   (coef [batch][2])
+// d = c1 d + c2 dinv (b - t); x = overwrite ? d : x + d   (coef [batch][2]);
+// clear_t / clear_b set t / b to zero after they are read
 template <typename T>
-void vcheb(T* x, T* d, const T* b, const T* t, const T* dinv, int64_t n, int batch,
-           const double* coef, bool overwrite, hipStream_t s);
+void vcheb(T* x, T* d, T* b, T* t, const T* dinv, int64_t n, int batch, const double* coef,
+           bool overwrite, bool clear_t, bool clear_b, hipStream_t s);
+// y += x, then x = 0 when clear_x
 template <typename T>
-void vaxpy(T* y, const T* x, int64_t n, hipStream_t s);
+void vaxpy(T* y, T* x, int64_t n, bool clear_x, hipStream_t s);
 template <typename T>
 void vinvert(T* x, int64_t n, hipStream_t s);
 void vrandom(double* x, int64_t n, uint64_t seed, hipStream_t s);

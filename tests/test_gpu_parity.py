@@ -202,6 +202,10 @@ def test_vcycle_matches_oracle(name):
     z_ref = osol.vcycle(levels, Ps, b, 3, 6)
     z = to_np(mg.vcycle(to_dev(b)))
     assert rel_l2(z, z_ref) <= TOL64
+    # cycles in a row: the work buffers must come back to their zero state
+    b2 = synth.uniform(501, spec.n_dof)
+    assert rel_l2(to_np(mg.vcycle(to_dev(b2))), osol.vcycle(levels, Ps, b2, 3, 6)) <= TOL64
+    assert rel_l2(to_np(mg.vcycle(to_dev(b))), z_ref) <= TOL64
 
 
 def test_lambda_estimate_bounds():
