@@ -38,17 +38,30 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def apply_kernel(spec):
+    """The kernel that performs y += A x for this workload, its source file, and
+    the model of the bytes one launch must move (one read of x, one read and one
+    write of y, the 6 stored G entries per quadrature point, plus per kernel:
+    1/det(sigma) per element for the GLL kernels, whose mass weight W|J| is
+    recovered from det G; W|J| per point and the element-to-node index for the
+    Gauss kernel; the index for the general GLL kernel, while the structured
+    lattice kernel computes node numbers)."""
+    P = spec.p + 1
+    if spec.quad == "gll":
+        return (f"ax_brick_kernel<double,{P}>", "ax_brick.hip",
+                "8*(x + y read + y write)*N + 48*n_elem*q^3 (G) + 8*n_elem (1/det sigma)")
+    return (f"ax_sem_kernel<double,{P},{spec.q}>", "ax.hip",
+            "8*(x + y read + y write)*N + 56*n_elem*q^3 (G, W|J|) + 4*n_elem*(p+1)^3 (index)")
+
+
 def algorithmic_bytes(spec, n_elem, n_dof, w, quad):
-    """Bytes an apply must move: x read, y write, the diagonal mass (SEM-NI) or
-    W|J| per point (SEM), the 6 stored G entries per quadrature point and the
-    element-to-node index."""
+    """Bytes one y += A x launch must move (see apply_kernel) in word size w."""
     q3 = spec.q ** 3
     P3 = (spec.p + 1) ** 3
     g = 6 * n_elem * q3 * w
-    idx = 4 * n_elem * P3
     if quad == "gll":
-        return 3 * w * n_dof + g + idx
-    return 2 * w * n_dof + w * n_elem * q3 + g + idx
+        return 3 * w * n_dof + g + w * n_elem
+    return 3 * w * n_dof + w * n_elem * q3 + g + 4 * n_elem * P3
 
 
 def algorithmic_flops(spec, n_elem, n_dof, quad):
@@ -58,11 +71,11 @@ def algorithmic_flops(spec, n_elem, n_dof, quad):
     return n_elem * (4 * (q * P ** 3 + q * q * P * P + q ** 3 * P) + 12 * q ** 4 + 17 * q ** 3)
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, source, workload):
     """HBM bytes per launch from the committed counter runs (profiles/counters.json),
     or None when the kernel source changed since they were taken."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2205_05136_amd", "csrc", "ax.hip")
+    src = os.path.join(ROOT, "paper_2205_05136_amd", "csrc", source)
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     try:
         entry = json.load(open(os.path.join(ROOT, "profiles", "counters.json"))).get(
@@ -232,8 +245,7 @@ def main():
     bytes32 = algorithmic_bytes(spec, spec.n_elem, N, 4, spec.quad)
     flops = algorithmic_flops(spec, spec.n_elem, N, spec.quad)
     achieved = bytes64 / (t_kernel * 1e-3) / 1e9
-    kname = (f"ax_ni_kernel<double,{spec.p + 1}>" if spec.quad == "gll"
-             else f"ax_sem_kernel<double,{spec.p + 1},{spec.q}>")
+    kname, ksrc, kmodel = apply_kernel(spec)
     out = {
         "metric": "operator-apply GDOF/s and PCG time-to-1e-10, FP64 vs mixed, p=2..7",
         "value": round(gdofs, 4),
@@ -261,10 +273,10 @@ def main():
                   "fp64_tflops": round(flops / (t_kernel * 1e-3) / 1e12, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(kname, args.workload),
+                     "traffic": measured_traffic(kname, ksrc, args.workload),
                      "kernel": kname,
                      "bytes_per_launch": int(bytes64),
-                     "bytes_model": "8*(x + y + diag mass)*N + 48*n_elem*q^3 (G) + 4*n_elem*(p+1)^3 (index)"},
+                     "bytes_model": kmodel},
     }
     if do_pcg:
         t64 = mean_ms(6, 7)

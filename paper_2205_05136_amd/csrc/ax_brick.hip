@@ -13,10 +13,13 @@
 //   4. the transposed 1D passes give each element node's result, which is added
 //      into an LDS copy of the lattice (LDS atomics: nodes shared by elements of
 //      the brick are summed on chip);
-//   5. lattice nodes that no other brick touches are written with plain stores,
-//      nodes on the brick's faces with global atomics.
-// Compared with one scatter-add per element node, the number of global atomics
-// and gathers drops by the brick's interior fraction (about half at p = 4).
+//   5. each lattice node of the brick is added into y with one global atomic.
+// Compared with one gather and one scatter-add per element node, global reads of
+// x and atomics drop from NE (p+1)^3 to (BX p+1)(BY p+1)(BZ p+1) per brick
+// (1000 -> 729 for the 2 x 2 x 2 bricks at p = 4), and no index array is read.
+// On small meshes (a few thousand elements) one- and two-element bricks, which give the grid
+// more waves, measured slower than these shapes: the extra global atomics on
+// shared nodes cost more than the added parallelism gains.
 #include "internal.hpp"
 
 namespace mfsem {

@@ -91,6 +91,34 @@ def test_apply_f64(name, spec, jit, sseed):
     assert rel_l2(d, A.diagonal()) <= TOL64
 
 
+# Structured meshes with enough elements for the large-brick launch shape of the
+# lattice kernel (small meshes take the small-brick shape), each with ragged
+# bricks on every axis: sampled rows against the oracle's element matrices, and
+# the whole vector against the general element kernel (itself pinned above).
+BRICK_CASES = [(1, (67, 33, 17)), (2, (41, 29, 9)), (4, (21, 17, 15)), (6, (17, 15, 9))]
+
+
+@pytest.mark.parametrize("p,n", BRICK_CASES, ids=[f"p{c[0]}" for c in BRICK_CASES])
+def test_apply_large_bricks(p, n):
+    announce(f"apply large bricks p{p} {n}")
+    spec = synth.slab(p, n)
+    box = mf.Box.from_spec(spec)
+    x = torch.sin(0.37 * torch.arange(spec.n_dof, device="cuda", dtype=torch.float64))
+    for store32 in (False, True):
+        lattice = mf.Operator.from_spec(spec, box=box, store_f32=store32)
+        general = mf.Operator.from_spec(spec, box=box, store_f32=store32, structured=False)
+        xs = x if not store32 else x.float()
+        y, yg = lattice.apply(xs), general.apply(xs)
+        assert rel_l2(to_np(y), to_np(yg)) <= (TOL64 if not store32 else TOL32)
+        if not store32:
+            rng = np.random.default_rng(p)
+            rows = np.concatenate([rng.integers(0, spec.n_dof, 24), [0, spec.n_dof - 1]])
+            ref = oop.apply_rows(spec, lambda g: np.sin(0.37 * np.asarray(g, dtype=np.float64)),
+                                 rows)
+            got = to_np(y[torch.as_tensor(rows, device="cuda")])
+            assert np.max(np.abs(got - ref)) <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("p,quad,q", [(2, "gll", 0), (4, "gll", 0), (7, "gll", 0), (4, "gauss", 6)])
 def test_apply_f32(p, quad, q):
     announce(f"apply f32 p{p} {quad}")
