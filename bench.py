@@ -7,15 +7,23 @@ p-coarsening 4 -> 2 -> 1 and Chebyshev degree 3, random right-hand side.
 
 One timed step = one pass of the hot path on that input:
   * R back-to-back operator applies y = A x (FP64; --apply-reps, default 20),
+    then R launches of the kernel alone (y += A x) in FP64 and in FP32,
   * one FP64 GMG-PCG solve A u = f to ||r||/||f|| <= 1e-10 from u0 = 0,
   * one mixed-precision solve (FP32 V-cycle inside FP64 flexible CG), same tolerance.
 `value` is the apply throughput in GDOF/s (unique mesh nodes per second) from
-HIP events around the back-to-back applies inside the timed steps (so host
-launch gaps do not count); the PCG times are reported beside it.  Set-up (geometry, diagonals, eigenvalue estimates) is
-outside the timed region, as in the paper.
+HIP events around the back-to-back applies inside the timed steps; the PCG
+times are reported beside it.  Set-up (geometry, diagonals, eigenvalue
+estimates) is outside the timed region, as in the paper.
 
-Other workloads (--workload): slab-p{2..7}[-gauss] (the sheared slab refined to
-about 51M DOFs), c3 / c3-gauss (128 x 48 x 24 at p = 7).
+Other workloads (--workload):
+  slab-p{2..7}[-gauss]  the sheared slab refined to about 51M DOFs (p-sweep),
+  c3 / c3-gauss         128 x 48 x 24 hexes at p = 7, SEM-NI / SEM (q = 9),
+  c4                    32^3 box at p = 4 with a batch of 8 per-element
+                        conductivity sets: the step's solve is a forward
+                        GMG-PCG plus the adjoint gradient dL/dsigma,
+  c5                    128 x 128 x 64 box at p = 5: the step's solve is one
+                        IMEX monodomain time step (run --steps 100 for the
+                        full 5 ms).
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
@@ -87,6 +95,15 @@ def measured_traffic(kernel, source, workload):
     return int(entry["read_bytes"] + entry["write_bytes"])
 
 
+def coarsening_for(p):
+    """p-coarsening by halving the degree down to 1 (4 -> 2 -> 1, 7 -> 3 -> 1)."""
+    chain, q = [], p
+    while q > 1:
+        q = max(1, q // 2)
+        chain.append(("p", q))
+    return tuple(chain)
+
+
 def workload(name):
     import synth
     if name == "c2":
@@ -102,6 +119,12 @@ def workload(name):
         return synth.C3_NI, "c3: sheared slab 128x48x24 hexes, p=7, SEM-NI (GLL)"
     if name == "c3-gauss":
         return synth.C3_SEM, "c3: sheared slab 128x48x24 hexes, p=7, SEM (Gauss q=9)"
+    if name == "c4":
+        return synth.C4, ("c4: box 16 mm, 32^3 hexes, p=4, SEM-NI, 8 per-element conductivity "
+                          "sets; forward GMG-PCG + adjoint gradient")
+    if name == "c5":
+        return synth.C5, ("c5: box 20x20x10 mm, 128x128x64 hexes, p=5, SEM-NI; IMEX monodomain "
+                          "steps (Aliev-Panfilov + mixed-precision GMG-PCG)")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -111,7 +134,7 @@ def cpu_baseline(spec, budget_s=20.0):
     import numpy as np
     import synth
     from oracle import operator as oop
-    if spec.n_dof > 3_000_000:
+    if spec.n_elem > 4000:
         # too large to assemble: rows of A x one by one from the element matrices
         x_fn = lambda g: np.sin(0.37 * np.asarray(g, dtype=np.float64))
         rng = np.random.default_rng(0)
@@ -125,7 +148,8 @@ def cpu_baseline(spec, budget_s=20.0):
         return {"value": rows / t / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
                 "sample": (f"oracle row-by-row apply (dense element matrices of the elements "
                            f"around each DOF) on {rows} random rows of the full mesh in {t:.1f} s; "
-                           f"the assembled matrix would not fit in host memory")}
+                           f"assembling the full matrix at {spec.n_elem:,} elements is beyond "
+                           f"this baseline's time budget")}
     t0 = time.perf_counter()
     prob = oop.Problem(spec)
     A, _, _ = prob.assemble()
@@ -169,32 +193,57 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     spec, desc = workload(args.workload)
+    kind = {"c4": "grad", "c5": "monodomain"}.get(args.workload, "pcg")
+    if args.no_pcg and kind == "pcg":
+        kind = None
     log(f"workload {args.workload}: {desc}; N = {spec.n_dof:,} DOFs, {spec.n_elem:,} elements")
     dev = "cuda"
     t0 = time.perf_counter()
-    coarsening = (("p", 2), ("p", 1)) if spec.p >= 3 else (("p", 1),)
-    do_pcg = not args.no_pcg
-    if do_pcg:
+    coarsening = coarsening_for(spec.p)
+    B = 1
+    extra = None
+    if kind == "pcg":
         ops, mg32 = mf.hierarchy(spec, coarsening=coarsening, degree=3, precision=torch.float32)
         op = ops[0]
         mg64 = mf.Multigrid(ops, mg32.transfers, degree=3, precision=torch.float64)
+        f = torch.as_tensor(synth.uniform(2, spec.n_dof), device=dev)
+    elif kind == "grad":
+        from paper_2205_05136_amd import autograd as ag
+        B = 8
+        sig = torch.as_tensor(synth.element_sigma(4, B, spec.n_elem), device=dev)
+        fB = torch.as_tensor(synth.uniform(5, (B, spec.n_dof)), device=dev)
+        ut = torch.as_tensor(synth.uniform(6, (B, spec.n_dof)), device=dev)
+        solver = ag.Solver(spec, batch=B, coarsening=coarsening, rtol=1e-10,
+                           precision=torch.float64)
+        solver.set_sigma(sig)
+        op = solver.ops[0]
+        op32 = None
+    elif kind == "monodomain":
+        from paper_2205_05136_amd.monodomain import Monodomain, Stimulus
+        sim = Monodomain(spec, dt=0.05, chi=synth.CHI, cm=synth.CM, ap_params=synth.AP_PARAMS,
+                         stimulus=Stimulus((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 50.0, 2.0),
+                         coarsening=coarsening, degree=3, precision=torch.float32)
+        op = sim.op
     else:
         op = mf.Operator.from_spec(spec, store_f32=True)
+    if kind == "grad":
+        # the FP32 kernel is timed on the same mesh with the constant conductivity
+        op32 = mf.Operator.from_spec(spec, store_f64=False, store_f32=True)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     log(f"set-up {t_setup:.2f} s")
 
-    x = torch.as_tensor(synth.uniform(100, spec.n_dof), device=dev)
-    f = torch.as_tensor(synth.uniform(2, spec.n_dof), device=dev)
+    N = spec.n_dof
+    x = torch.as_tensor(synth.uniform(100, B * N), device=dev)   # [batch][N], flattened
     y = torch.empty_like(x)
-    x32 = x.float()
+    x32 = torch.as_tensor(synth.uniform(100, N), device=dev).float()
     y32 = torch.empty_like(x32)
+    opf = op if kind != "grad" else op32
     E = lambda: torch.cuda.Event(enable_timing=True)
-
     R = args.apply_reps
 
     def step(rec):
-        ev = [E() for _ in range(10)]
+        ev = [E() for _ in range(8)]
         ev[0].record()
         for _ in range(R):
             op.apply(x, out=y)                 # full apply: clear y + operator kernel
@@ -207,19 +256,29 @@ def main():
         y32.zero_()
         ev[4].record()
         for _ in range(R):
-            op.apply_add(x32, y32)             # FP32 operator kernel
+            opf.apply_add(x32, y32)            # FP32 operator kernel
         ev[5].record()
-        it64 = it32 = None
-        if do_pcg:
-            ev[6].record()
+        if kind == "pcg":
             u64, i64 = mf.pcg(op, f, mg=mg64, rtol=1e-10, max_it=200)
-            ev[7].record()
+            ev[6].record()
             u32, i32 = mf.pcg(op, f, mg=mg32, rtol=1e-10, max_it=200)
-            ev[8].record()
-            it64, it32 = i64.iters[0], i32.iters[0]
+            ev[7].record()
             rec.setdefault("sol", (u64, u32))
+            rec.setdefault("its", []).append((i64.iters[0], i32.iters[0]))
+        elif kind == "grad":
+            s = sig.clone().requires_grad_(True)
+            u = ag.solve(s, fB, solver)
+            ev[6].record()
+            loss = 0.5 * ((u - ut) ** 2).sum()
+            loss.backward()
+            ev[7].record()
+            rec.setdefault("grad", s.grad)
+        elif kind == "monodomain":
+            info = sim.step()
+            ev[6].record()
+            ev[7].record()
+            rec.setdefault("its", []).append(info.iters[0])
         rec.setdefault("ev", []).append(ev)
-        rec.setdefault("its", []).append((it64, it32))
 
     warm = {}
     for _ in range(args.warmup):
@@ -239,11 +298,11 @@ def main():
     t_apply = mean_ms(0, 1) / R
     t_kernel = mean_ms(2, 3) / R
     t_kernel32 = mean_ms(4, 5) / R
-    N = spec.n_dof
-    gdofs = N / (t_apply * 1e-3) / 1e9
-    bytes64 = algorithmic_bytes(spec, spec.n_elem, N, 8, spec.quad)
+    NB = N * B
+    gdofs = NB / (t_apply * 1e-3) / 1e9
+    bytes64 = B * algorithmic_bytes(spec, spec.n_elem, N, 8, spec.quad)
     bytes32 = algorithmic_bytes(spec, spec.n_elem, N, 4, spec.quad)
-    flops = algorithmic_flops(spec, spec.n_elem, N, spec.quad)
+    flops = B * algorithmic_flops(spec, spec.n_elem, N, spec.quad)
     achieved = bytes64 / (t_kernel * 1e-3) / 1e9
     kname, ksrc, kmodel = apply_kernel(spec)
     out = {
@@ -259,14 +318,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "n_dof": N, "n_elem": spec.n_elem, "p": spec.p,
+        "config": {"workload": desc, "n_dof": N, "batch": B, "n_elem": spec.n_elem, "p": spec.p,
                    "quadrature": spec.quad, "nq1d": spec.q, "alpha": spec.alpha,
                    "sigma_mS_per_mm": list(spec.sigma),
                    "multigrid": "p " + "->".join([str(spec.p)] + [str(c[1]) for c in coarsening])
                                 + ", Chebyshev degree 3 on [0.08, 1.2]*lambda_max (10 CG steps)",
                    "parallelism": "single GPU"},
         "apply": {"reps_per_step": R, "fp64_ms": round(t_apply, 5), "fp64_kernel_ms": round(t_kernel, 5),
-                  "fp64_kernel_gdofs": round(N / (t_kernel * 1e-3) / 1e9, 3),
+                  "fp64_kernel_gdofs": round(NB / (t_kernel * 1e-3) / 1e9, 3),
                   "fp32_kernel_ms": round(t_kernel32, 5),
                   "fp32_kernel_gdofs": round(N / (t_kernel32 * 1e-3) / 1e9, 3),
                   "fp32_hbm_frac": round(bytes32 / (t_kernel32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -278,27 +337,47 @@ def main():
                      "bytes_per_launch": int(bytes64),
                      "bytes_model": kmodel},
     }
-    if do_pcg:
-        t64 = mean_ms(6, 7)
-        t32 = mean_ms(7, 8)
+    if kind == "pcg":
+        t64 = mean_ms(5, 6)
+        t32 = mean_ms(6, 7)
         u64, u32 = rec["sol"]
         r = f - op.apply(u64)
         rel_res = float(torch.linalg.norm(r) / torch.linalg.norm(f))
+        r32 = f - op.apply(u32)
+        rel_res32 = float(torch.linalg.norm(r32) / torch.linalg.norm(f))
         rel_mixed = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
         lam64 = mg64.lambdas()[:, 0].tolist()
         out["pcg"] = {"fp64_ms": round(t64, 4), "mixed_ms": round(t32, 4),
                       "fp64_iters": rec["its"][0][0], "mixed_iters": rec["its"][0][1],
-                      "fp64_true_rel_residual": rel_res,
+                      "fp64_true_rel_residual": rel_res, "mixed_true_rel_residual": rel_res32,
                       "mixed_vs_fp64_rel_l2": rel_mixed,
                       "lambda_max_per_level": [round(v, 5) for v in lam64],
                       "tol": 1e-10, "x0": "zero", "setup_s": round(t_setup, 3)}
+    elif kind == "grad":
+        g = rec["grad"]
+        out["grad"] = {"batch": B, "forward_solve_ms": round(mean_ms(5, 6), 4),
+                       "backward_ms": round(mean_ms(6, 7), 4),
+                       "backward": "adjoint GMG-PCG (FP64, rtol 1e-10) + per-element dA/dsigma contraction",
+                       "grad_finite": bool(torch.isfinite(g).all()),
+                       "setup_s": round(t_setup, 3)}
+    elif kind == "monodomain":
+        its = rec["its"]
+        st = sim.stats
+        k = len(its)
+        out["monodomain"] = {"time_steps_timed": k, "dt_ms": 0.05,
+                             "ms_per_time_step": round(mean_ms(5, 6), 4),
+                             "ionic_rhs_ms": round(sum(st.ionic_ms[-k:]) / k, 4),
+                             "solve_ms": round(sum(st.solve_ms[-k:]) / k, 4),
+                             "pcg_iters_mean": round(sum(its) / k, 3),
+                             "V_range_mV": [round(float(sim.V.min()), 3), round(float(sim.V.max()), 3)],
+                             "sim_time_ms": round(sim.t, 4), "setup_s": round(t_setup, 3)}
     if args.copy_ref:
         # y = x + 0: reads 8N and writes 8N bytes; its counter readings calibrate
         # the FETCH_SIZE / WRITE_SIZE of the operator kernel
         for _ in range(3):
             torch.add(x, 0.0, out=y)
         torch.cuda.synchronize()
-        out["copy_ref_bytes"] = {"read": 8 * N, "write": 8 * N}
+        out["copy_ref_bytes"] = {"read": 8 * NB, "write": 8 * NB}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(spec)
