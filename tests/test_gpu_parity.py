@@ -85,16 +85,20 @@ def test_apply_f64(name, spec, jit, sseed):
     x = synth.uniform(100, spec.n_dof)
     y = to_np(op.apply(to_dev(x)))
     assert rel_l2(y, A @ x) <= TOL64
+    if spec.quad == "gll":
+        # the general element-map kernel (GLL meshes take the lattice kernel by default)
+        opg, _ = _op(spec, jitter=jit, sigma=sigma, structured=False)
+        assert rel_l2(to_np(opg.apply(to_dev(x))), A @ x) <= TOL64
     ym = to_np(op.apply_mass(to_dev(x)))
     assert rel_l2(ym, M @ x) <= TOL64
     d = to_np(op.diagonal())
     assert rel_l2(d, A.diagonal()) <= TOL64
 
 
-# Structured meshes with enough elements for the large-brick launch shape of the
-# lattice kernel (small meshes take the small-brick shape), each with ragged
-# bricks on every axis: sampled rows against the oracle's element matrices, and
-# the whole vector against the general element kernel (itself pinned above).
+# Structured meshes of hundreds of lattice-kernel bricks (more than a workgroup
+# per CU), each with ragged bricks on every axis the brick shape splits: sampled
+# rows against the oracle's element matrices, and the whole vector against the
+# general element kernel (itself pinned above).
 BRICK_CASES = [(1, (67, 33, 17)), (2, (41, 29, 9)), (4, (21, 17, 15)), (6, (17, 15, 9))]
 
 
