@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MFSEM_ABI_VERSION 1
+#define MFSEM_ABI_VERSION 2
 #define MFSEM_MAX_P 8
 
 typedef enum {
@@ -60,6 +60,16 @@ typedef enum {
 typedef enum { MFSEM_GLL = 0, /* SEM-NI */ MFSEM_GAUSS = 1 /* SEM */ } mfsem_quad;
 typedef enum { MFSEM_F64 = 0, MFSEM_F32 = 1 } mfsem_dtype;
 typedef enum { MFSEM_TRANSFER_P = 0, MFSEM_TRANSFER_H = 1 } mfsem_transfer_kind;
+/* Where the FP64 stiffness apply takes W|J| J^{-1} sigma J^{-T} from (Section 4:
+ * the Jacobian may be cached or evaluated in the cell loop).  On MI355X the
+ * stored values are faster at every degree (the on-the-fly kernel moves about
+ * 40% fewer bytes but is bound by its FP64 arithmetic and LDS reads), so AUTO
+ * selects them. */
+typedef enum {
+  MFSEM_GEOM_AUTO = 0,      /* the library's choice: stored */
+  MFSEM_GEOM_STORED = 1,    /* the values stored at create */
+  MFSEM_GEOM_ONTHEFLY = 2   /* on the fly; EINVAL if the operator is not eligible */
+} mfsem_geometry;
 
 typedef struct mfsem_op mfsem_op;
 typedef struct mfsem_mg mfsem_mg;
@@ -143,6 +153,15 @@ typedef struct {
                                   numbering of mfsem_box_generate (checked at create;
                                   EINVAL if it is not), enabling the brick kernels;
                                   {0,0,0} for any other mesh                           */
+  int32_t geometry;            /* mfsem_geometry.  On the fly, the FP64 apply recomputes
+                                  J from the lattice's map_xyz and G from the fiber and
+                                  sigma at every point instead of reading the stored G
+                                  (48 bytes per point -> 48 bytes per node); eligible:
+                                  structured lattice, GLL, p <= 6, map = DOF nodes
+                                  (map_p == p, map_elem_dof NULL or elem_dof,
+                                  n_map_nodes == n_dof), no sheet, store_f64.  FP32 calls,
+                                  the diagonal, the mass and the gradient always use the
+                                  stored values.                                       */
 } mfsem_op_desc;
 
 /* Workspace an operator needs. [host] */

@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EGEOMETRY", -4: 
 MFSEM_GLL, MFSEM_GAUSS = 0, 1
 MFSEM_F64, MFSEM_F32 = 0, 1
 MFSEM_TRANSFER_P, MFSEM_TRANSFER_H = 0, 1
+MFSEM_GEOM_AUTO, MFSEM_GEOM_STORED, MFSEM_GEOM_ONTHEFLY = 0, 1, 2
 MAX_P = 8
 
 
@@ -38,7 +39,7 @@ class OpDesc(C.Structure):
                 ("map_xyz", C.c_void_p), ("fiber", C.c_void_p), ("sheet", C.c_void_p),
                 ("sigma", C.c_void_p), ("sigma_const", C.c_double * 3), ("batch", C.c_int32),
                 ("alpha", C.c_double), ("store_f64", C.c_int32), ("store_f32", C.c_int32),
-                ("lattice", C.c_int32 * 3)]
+                ("lattice", C.c_int32 * 3), ("geometry", C.c_int32)]
 
 
 class TransferDesc(C.Structure):

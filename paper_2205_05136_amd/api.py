@@ -87,11 +87,17 @@ class Operator:
     """A = alpha*M + K(sigma) on a mesh (mfsem_op_*).
 
     dofs: Box giving the DOF numbering (degree p); geometry: Box giving the map
-    (defaults to `dofs`); xyz/fiber override the map's node data (e.g. jitter)."""
+    (defaults to `dofs`); xyz/fiber override the map's node data (e.g. jitter).
+    geom: "auto" | "stored" | "onthefly" (mfsem_geometry): where the FP64
+    stiffness apply takes G = W|J| J^-1 sigma J^-T from."""
+
+    GEOM = {"auto": L.MFSEM_GEOM_AUTO, "stored": L.MFSEM_GEOM_STORED,
+            "onthefly": L.MFSEM_GEOM_ONTHEFLY}
 
     def __init__(self, dofs: Box, geometry: Box | None = None, quad="gll", nq1d=0, sigma=None,
                  sigma_const=(1.0, 1.0, 1.0), batch=1, alpha=1.0, store_f64=True,
-                 store_f32=False, xyz=None, fiber="geometry", sheet=None, structured=True):
+                 store_f32=False, xyz=None, fiber="geometry", sheet=None, structured=True,
+                 geom="auto"):
         lib = L.load()
         geo = geometry or dofs
         self.dofs, self.geometry = dofs, geo
@@ -116,7 +122,8 @@ class Operator:
             map_xyz=self.xyz.data_ptr(), fiber=_ptr(self.fiber).value, sheet=_ptr(sheet).value,
             sigma=_ptr(sigma).value, sigma_const=(C.c_double * 3)(*sigma_const), batch=batch,
             alpha=alpha, store_f64=int(store_f64), store_f32=int(store_f32),
-            lattice=(C.c_int32 * 3)(*(dofs.n if structured else (0, 0, 0))))
+            lattice=(C.c_int32 * 3)(*(dofs.n if structured else (0, 0, 0))),
+            geometry=self.GEOM[geom])
         nbytes = C.c_size_t()
         L.check(lib.mfsem_op_workspace_bytes(C.byref(self.desc), C.byref(nbytes)))
         self.ws = _workspace(nbytes.value, self.device)

@@ -65,6 +65,15 @@ void box_counts(const mfsem_box_desc* b, int64_t* ne, int64_t* nd) {
   *nd = ((int64_t)b->p * b->n[0] + 1) * ((int64_t)b->p * b->n[1] + 1) * ((int64_t)b->p * b->n[2] + 1);
 }
 
+// The FP64 stiffness apply can rebuild G from the node lattice when the map
+// nodes are the DOF nodes of a structured GLL lattice (points = nodes).
+bool onthefly_eligible(const mfsem_op_desc* d) {
+  const int mp = d->map_p == 0 ? d->p : d->map_p;
+  return d->lattice[0] > 0 && d->quad == MFSEM_GLL && mp == d->p && d->p <= 6 &&
+         (d->map_elem_dof == nullptr || d->map_elem_dof == d->elem_dof) &&
+         d->n_map_nodes == d->n_dof && d->sheet == nullptr && d->store_f64;
+}
+
 void validate_op(const mfsem_op_desc* d) {
   require(d != nullptr, "operator descriptor is NULL");
   require(d->p >= 1 && d->p <= MFSEM_MAX_P, "p must be in 1..MFSEM_MAX_P");
@@ -96,6 +105,13 @@ void validate_op(const mfsem_op_desc* d) {
                        ((int64_t)d->p * d->lattice[2] + 1);
     require(nd == d->n_dof, "lattice counts do not give n_dof");
   }
+  require(d->geometry >= MFSEM_GEOM_AUTO && d->geometry <= MFSEM_GEOM_ONTHEFLY,
+          "geometry must be MFSEM_GEOM_AUTO, _STORED or _ONTHEFLY");
+  if (d->geometry == MFSEM_GEOM_ONTHEFLY)
+    require(onthefly_eligible(d),
+            "on-the-fly geometry needs a structured lattice, GLL quadrature, p <= 6, the map on "
+            "the DOF nodes (map_p == p, map_elem_dof NULL or elem_dof, n_map_nodes == n_dof), "
+            "no sheet and store_f64");
 }
 
 void op_init(mfsem_op& op, const mfsem_op_desc* d) {
@@ -110,6 +126,7 @@ void op_init(mfsem_op& op, const mfsem_op_desc* d) {
   op.off = table_offsets(op.P, op.Q, op.Pm);
   op.structured = d->lattice[0] > 0;
   for (int i = 0; i < 3; ++i) op.lat[i] = d->lattice[i];
+  op.otf = d->geometry == MFSEM_GEOM_ONTHEFLY;  // validated as eligible
 }
 
 void check_op(const mfsem_op* op, int dtype) {

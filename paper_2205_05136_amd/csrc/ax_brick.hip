@@ -50,6 +50,9 @@ struct BrickCfg {
   static constexpr int LN = LX * LY * LZ;
   static constexpr int THREADS = r64(NE * P2);
   static constexpr int WAVES = BrickShape<P>::W;
+  // with on-the-fly geometry (FP64): the extra live values of the Jacobian fit
+  // in the register budget of at most 2 waves per SIMD from P = 5 on
+  static constexpr int WAVES_OTF = P >= 5 ? 2 : BrickShape<P>::W;
 };
 
 template <typename T>
@@ -57,11 +60,82 @@ __device__ inline void lds_add(T* p, T v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <typename T, int P>
-__global__ __launch_bounds__(BrickCfg<P>::THREADS, BrickCfg<P>::WAVES) void ax_brick_kernel(
+// OTF: G and the mass weight are rebuilt at every point from the brick's node
+// coordinates (staged in LDS, in the space the fluxes use later), the fiber at
+// the point and the element's (sigma_l, sigma_t), instead of being read from
+// the stored G: with C the cofactor matrix of J (J^{-1} = C^T / det J),
+//   G = W |J| J^{-1} sigma J^{-T} = (W / det J) C^T sigma C,
+//   sigma = sigma_t I + (sigma_l - sigma_t) f f^T / |f|^2,
+// so G = (W / det J) (sigma_t C^T C + (sigma_l - sigma_t) v v^T / |f|^2), v = C^T f,
+// and W |J| = W det J.  GLL points are the element's nodes, so J comes from the
+// same 1D derivative rows as the gradient and f is the nodal fiber.
+// G (6 values) and W|J| at point c of a lane's pencil from the LDS lattice
+// coordinates cs [3][LN]; xk holds the coordinates along the pencil.
+template <typename T, int P, int LX, int LY, int LN>
+__device__ inline void otf_point(const T* cs, int o, int ia, int ib, int c, const T (&dx)[P],
+                                 const T (&dy)[P], const T* Dtab, const T (&xk)[3][P],
+                                 const T (&f)[3], bool has_fiber, T sl, T st, T W, T (&g)[6],
+                                 T& wj) {
+  T J[3][3];  // J[r][d] = d X_r / d xi_d
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    T a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      a0 += dx[m] * cs[r * LN + o - ia + m + LX * LY * c];
+      a1 += dy[m] * cs[r * LN + o - LX * ib + LX * m + LX * LY * c];
+      a2 += Dtab[c * P + m] * xk[r][m];
+    }
+    J[r][0] = a0;
+    J[r][1] = a1;
+    J[r][2] = a2;
+  }
+  // cofactors C[r][d]
+  const T c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  const T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  const T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  const T c10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  const T c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  const T c12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  const T c20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  const T c21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  const T c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const T det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+  const T sc = W / det;
+  T m00 = st * (c00 * c00 + c10 * c10 + c20 * c20);
+  T m01 = st * (c00 * c01 + c10 * c11 + c20 * c21);
+  T m02 = st * (c00 * c02 + c10 * c12 + c20 * c22);
+  T m11 = st * (c01 * c01 + c11 * c11 + c21 * c21);
+  T m12 = st * (c01 * c02 + c11 * c12 + c21 * c22);
+  T m22 = st * (c02 * c02 + c12 * c12 + c22 * c22);
+  if (has_fiber) {
+    const T v0 = c00 * f[0] + c10 * f[1] + c20 * f[2];
+    const T v1 = c01 * f[0] + c11 * f[1] + c21 * f[2];
+    const T v2 = c02 * f[0] + c12 * f[1] + c22 * f[2];
+    const T kf = (sl - st) / (f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    m00 += kf * v0 * v0;
+    m01 += kf * v0 * v1;
+    m02 += kf * v0 * v2;
+    m11 += kf * v1 * v1;
+    m12 += kf * v1 * v2;
+    m22 += kf * v2 * v2;
+  }
+  g[0] = sc * m00;
+  g[1] = sc * m01;
+  g[2] = sc * m02;
+  g[3] = sc * m11;
+  g[4] = sc * m12;
+  g[5] = sc * m22;
+  wj = W * det;
+}
+
+template <typename T, int P, bool OTF>
+__global__ __launch_bounds__(BrickCfg<P>::THREADS,
+                             OTF ? BrickCfg<P>::WAVES_OTF : BrickCfg<P>::WAVES) void ax_brick_kernel(
     int nx, int ny, int nz, int64_t n_dof, const T* __restrict__ G, const T* __restrict__ WJ,
-    const T* __restrict__ idet, T alpha, const T* __restrict__ Dtab, const T* __restrict__ wtab,
-    const T* __restrict__ x, T* __restrict__ y) {
+    const T* __restrict__ idet, const double* __restrict__ xyz, const double* __restrict__ fiber,
+    const double* __restrict__ sig, double s_l, double s_t, T alpha, const T* __restrict__ Dtab,
+    const T* __restrict__ wtab, const T* __restrict__ x, T* __restrict__ y) {
   using C = BrickCfg<P>;
   constexpr int p = C::p, P2 = C::P2, P3 = C::P3, NE = C::NE;
   constexpr int BX = C::BX, BY = C::BY, BZ = C::BZ, LX = C::LX, LY = C::LY, LN = C::LN;
@@ -70,6 +144,7 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS, BrickCfg<P>::WAVES) void ax_b
   __shared__ T xs[LN];
   __shared__ T ys[LN];
   __shared__ T F[NE * 2 * P3];
+  __shared__ T cs[OTF ? 3 * LN : 1];  // OTF: lattice coordinates [3][LN]
 
   const int tid = threadIdx.x;
   const int nbx = (nx + BX - 1) / BX, nby = (ny + BY - 1) / BY;
@@ -107,7 +182,36 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS, BrickCfg<P>::WAVES) void ax_b
   }
   T g[P][6];
   T id = 0;
-  if (active) {
+  // OTF: the lattice coordinates, the fiber at the pencil's points, sigma
+  T cv[OTF ? 3 * NIT : 1];
+  T fv[OTF ? P : 1][3];
+  T sl = 0, st = 0;
+  if constexpr (OTF) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int n = tid + it * C::THREADS;
+      const int i = n % LX, j = (n / LX) % LY, k = n / (LX * LY);
+      const bool in = n < LN && i <= nex * p && j <= ney * p && k <= nez * p;
+      const double* src = xyz + 3 * ((I0 + i) + NX * ((J0 + j) + NY * (K0 + k)));
+#pragma unroll
+      for (int r = 0; r < 3; ++r) cv[3 * it + r] = in ? src[r] : T(0);
+    }
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const int64_t node = (I0 + lx * p + ia) + NX * ((J0 + ly * p + ib) + NY * (K0 + lz * p + c));
+#pragma unroll
+        for (int r = 0; r < 3; ++r) fv[c][r] = fiber ? fiber[3 * node + r] : T(0);
+      }
+      if (sig) {
+        sl = sig[((int64_t)bt * ne_tot + e) * 3];
+        st = sig[((int64_t)bt * ne_tot + e) * 3 + 1];
+      } else {
+        sl = s_l;
+        st = s_t;
+      }
+    }
+  } else if (active) {
     const T* Ge = G + (((int64_t)bt * ne_tot + e) * P3 + ab) * 6;
 #pragma unroll
     for (int c = 0; c < P; ++c) load_g6(Ge + c * P2 * 6, g[c]);
@@ -121,27 +225,40 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS, BrickCfg<P>::WAVES) void ax_b
     if (n < LN) {
       xs[n] = xv[it];
       ys[n] = 0;
+      if constexpr (OTF) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) cs[r * LN + n] = cv[3 * it + r];
+      }
     }
   }
   __syncthreads();
 
-  // 2-3. per point of the pencil: reference gradient from the LDS lattice,
-  // fluxes (two to LDS, one kept in registers) and the mass term
+  // this lane's rows of the 1D derivative matrix stay in registers; the
+  // lane-uniform entries of the third direction come from scalar loads
+  T dx[P], dy[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    dx[m] = sD[ia * P + m];
+    dy[m] = sD[ib * P + m];
+  }
+  const T wab = sw[ia] * sw[ib];
+
   T u[P], ft[P], out[P];
   if (active) {
 #pragma unroll
     for (int c = 0; c < P; ++c) u[c] = xs[o + LX * LY * c];
-    const T wab = sw[ia] * sw[ib];
-    // this lane's rows of the 1D derivative matrix stay in registers; the
-    // lane-uniform entries of the third direction come from scalar loads
-    T dx[P], dy[P];
+    T xk[OTF ? 3 : 1][P];  // OTF: coordinates along the pencil
+    if constexpr (OTF) {
 #pragma unroll
-    for (int m = 0; m < P; ++m) {
-      dx[m] = sD[ia * P + m];
-      dy[m] = sD[ib * P + m];
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int m = 0; m < P; ++m) xk[r][m] = cs[r * LN + o + LX * LY * m];
     }
 #pragma unroll
     for (int c = 0; c < P; ++c) {
+      T wjo = 0;
+      if constexpr (OTF) otf_point<T, P, LX, LY, LN>(cs, o, ia, ib, c, dx, dy, Dtab, xk, fv[c],
+                                                    fiber != nullptr, sl, st, wab * sw[c], g[c], wjo);
       const T g00 = g[c][0], g01 = g[c][1], g02 = g[c][2];
       const T g11 = g[c][3], g12 = g[c][4], g22 = g[c][5];
       T r = 0, s = 0, t = 0;
@@ -156,7 +273,9 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS, BrickCfg<P>::WAVES) void ax_b
       Fe[P3 + q] = g01 * r + g11 * s + g12 * t;
       ft[c] = g02 * r + g12 * s + g22 * t;
       T wj;
-      if (idet) {
+      if constexpr (OTF) {
+        wj = wjo;
+      } else if (idet) {
         const T W = wab * sw[c];
         const T dG = g00 * (g11 * g22 - g12 * g12) - g01 * (g01 * g22 - g12 * g02) +
                      g02 * (g01 * g12 - g11 * g02);
@@ -207,8 +326,22 @@ void run(const mfsem_op& op, const T* G, const T* WJ, const T* idet, const T* ta
   const int nx = op.lat[0], ny = op.lat[1], nz = op.lat[2];
   const int64_t nb = (int64_t)((nx + C::BX - 1) / C::BX) * ((ny + C::BY - 1) / C::BY) *
                      ((nz + C::BZ - 1) / C::BZ);
-  ax_brick_kernel<T, P><<<dim3((unsigned)nb, op.d.batch), dim3(C::THREADS), 0, s>>>(
-      nx, ny, nz, op.d.n_dof, G, WJ, idet, alpha, tab + op.off.Db, tab + op.off.w, x, y);
+  const dim3 grid((unsigned)nb, op.d.batch), block(C::THREADS);
+  const double sl = op.d.sigma_const[0], st = op.d.sigma_const[1];
+  // on-the-fly geometry up to P = 7: at P = 8 the coordinate lattice leaves
+  // LDS for one workgroup per CU (the operator's eligibility check matches)
+  if constexpr (sizeof(T) == sizeof(double) && P <= 7) {
+    if (op.otf) {
+      ax_brick_kernel<T, P, true><<<grid, block, 0, s>>>(
+          nx, ny, nz, op.d.n_dof, nullptr, nullptr, nullptr, op.d.map_xyz, op.d.fiber,
+          op.sigma_copy, sl, st, alpha, tab + op.off.Db, tab + op.off.w, x, y);
+      MFSEM_LAUNCH("ax_brick_kernel (on-the-fly geometry)");
+      return;
+    }
+  }
+  ax_brick_kernel<T, P, false><<<grid, block, 0, s>>>(
+      nx, ny, nz, op.d.n_dof, G, WJ, idet, nullptr, nullptr, nullptr, sl, st, alpha,
+      tab + op.off.Db, tab + op.off.w, x, y);
   MFSEM_LAUNCH("ax_brick_kernel");
 }
 

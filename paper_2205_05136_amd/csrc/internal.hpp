@@ -122,6 +122,8 @@ struct mfsem_op {
   // structured lattice (elements per axis) when elem_dof follows the box numbering
   bool structured = false;
   int lat[3] = {0, 0, 0};
+  // the FP64 stiffness apply rebuilds G from map_xyz, fiber and sigma
+  bool otf = false;
   // [0]: first failing (element, point) of the geometry; [1]: elements with
   // det(sigma) <= 0; [2]: element nodes that differ from the structured numbering
   unsigned long long* bad = nullptr;

@@ -31,17 +31,19 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
     # and the binding declares a prototype for each
     assert set(names) <= set(L.PROTOTYPES), set(names) - set(L.PROTOTYPES)
-    assert lib.mfsem_abi_version() == 1
+    hdr = open(os.path.join(ROOT, "include", "mfsem.h")).read()
+    assert f"#define MFSEM_ABI_VERSION {lib.mfsem_abi_version()}\n" in hdr
 
 
 def test_struct_layouts_match_header(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mfsem.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                     'sizeof(mfsem_box_desc), sizeof(mfsem_op_desc), sizeof(mfsem_mg_desc),'
                     'sizeof(mfsem_transfer_desc), sizeof(mfsem_solve_opts), sizeof(mfsem_solve_info),'
                     'sizeof(mfsem_ap_params), offsetof(mfsem_op_desc, alpha),'
-                    'offsetof(mfsem_mg_desc, precision));return 0;}\n')
+                    'offsetof(mfsem_op_desc, geometry), offsetof(mfsem_mg_desc, precision));'
+                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
                    check=True)
@@ -49,7 +51,8 @@ def test_struct_layouts_match_header(tmp_path):
                                           check=True).stdout.split()]
     want = [C.sizeof(L.BoxDesc), C.sizeof(L.OpDesc), C.sizeof(L.MgDesc),
             C.sizeof(L.TransferDesc), C.sizeof(L.SolveOpts), C.sizeof(L.SolveInfo),
-            C.sizeof(L.APParams), L.OpDesc.alpha.offset, L.MgDesc.precision.offset]
+            C.sizeof(L.APParams), L.OpDesc.alpha.offset, L.OpDesc.geometry.offset,
+            L.MgDesc.precision.offset]
     assert got == want
 
 
@@ -90,7 +93,9 @@ def test_op_workspace_query_and_validation():
     bad = [dict(p=0), dict(p=9), dict(quad=5), dict(nq1d=7), dict(quad=L.MFSEM_GAUSS, nq1d=4),
            dict(quad=L.MFSEM_GAUSS, nq1d=9), dict(batch=0), dict(alpha=-1.0),
            dict(store_f64=0, store_f32=0), dict(map_p=3), dict(elem_dof=None),
-           dict(sheet=5), dict(n_dof=2 ** 31)]
+           dict(sheet=5), dict(n_dof=2 ** 31), dict(geometry=3), dict(geometry=-1),
+           # on-the-fly geometry needs a structured GLL lattice whose map is the DOF nodes
+           dict(geometry=L.MFSEM_GEOM_ONTHEFLY)]
     for kw in bad:
         assert lib.mfsem_op_workspace_bytes(C.byref(_op_desc(**kw)), C.byref(nb)) == -1, kw
         assert lib.mfsem_last_error()

@@ -86,9 +86,13 @@ def test_apply_f64(name, spec, jit, sseed):
     y = to_np(op.apply(to_dev(x)))
     assert rel_l2(y, A @ x) <= TOL64
     if spec.quad == "gll":
-        # the general element-map kernel (GLL meshes take the lattice kernel by default)
-        opg, _ = _op(spec, jitter=jit, sigma=sigma, structured=False)
-        assert rel_l2(to_np(opg.apply(to_dev(x))), A @ x) <= TOL64
+        # GLL lattices take the lattice kernel on stored G by default; the same
+        # kernel with on-the-fly geometry (p <= 6), and the general element-map
+        # kernel, must agree with the oracle too
+        variants = [dict(structured=False)] + ([dict(geom="onthefly")] if spec.p <= 6 else [])
+        for kw in variants:
+            opv, _ = _op(spec, jitter=jit, sigma=sigma, **kw)
+            assert rel_l2(to_np(opv.apply(to_dev(x))), A @ x) <= TOL64, kw
     ym = to_np(op.apply_mass(to_dev(x)))
     assert rel_l2(ym, M @ x) <= TOL64
     d = to_np(op.diagonal())
@@ -114,6 +118,9 @@ def test_apply_large_bricks(p, n):
         xs = x if not store32 else x.float()
         y, yg = lattice.apply(xs), general.apply(xs)
         assert rel_l2(to_np(y), to_np(yg)) <= (TOL64 if not store32 else TOL32)
+        if not store32:  # the lattice kernel with on-the-fly geometry as well
+            otf = mf.Operator.from_spec(spec, box=box, geom="onthefly")
+            assert rel_l2(to_np(otf.apply(xs)), to_np(yg)) <= TOL64
         if not store32:
             rng = np.random.default_rng(p)
             rows = np.concatenate([rng.integers(0, spec.n_dof, 24), [0, spec.n_dof - 1]])
@@ -144,9 +151,12 @@ def test_apply_batch_sigma():
     op = mf.Operator.from_spec(spec, box=box, sigma=to_dev(sig))
     x = synth.uniform(102, (3, spec.n_dof))
     y = to_np(op.apply(to_dev(x)))
+    otf = mf.Operator.from_spec(spec, box=box, sigma=to_dev(sig), geom="onthefly")
+    y_otf = to_np(otf.apply(to_dev(x)))
     for b in range(3):
         A, _, _ = oop.Problem(spec, sigma=sig[b]).assemble()
         assert rel_l2(y[b], A @ x[b]) <= TOL64
+        assert rel_l2(y_otf[b], A @ x[b]) <= TOL64
     # set_sigma recomputes the geometry
     sig2 = sig[::-1].copy()
     op.set_sigma(to_dev(sig2))
@@ -348,6 +358,14 @@ def test_error_paths():
     assert e.value.status == -3 and "element 0" in str(e.value)
     with pytest.raises(mf.MfsemError) as e:
         mf.Operator.from_spec(spec, box=box, quad="gll", nq1d=spec.p + 2)
+    assert e.value.status == -1
+    # on-the-fly geometry refused where it does not apply (Gauss points, p = 7)
+    with pytest.raises(mf.MfsemError) as e:
+        mf.Operator.from_spec(spec, box=box, quad="gauss", nq1d=spec.p + 1, geom="onthefly")
+    assert e.value.status == -1 and "on-the-fly" in str(e.value)
+    spec7 = _spec(7, (1, 1, 1))
+    with pytest.raises(mf.MfsemError) as e:
+        mf.Operator.from_spec(spec7, geom="onthefly")
     assert e.value.status == -1
     op = mf.Operator.from_spec(spec, box=box)
     f = to_dev(synth.uniform(1, spec.n_dof))
