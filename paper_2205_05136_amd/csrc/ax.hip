@@ -122,7 +122,8 @@ __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
 #pragma unroll
     for (int c = 0; c < P; ++c) load_g6(Ge + c * P2 * 6, g[c]);
     const T id = idet ? idet[(int64_t)bt * n_elem + e] : T(0);
-    const T wab = idet ? wtab[ia] * wtab[ib] : T(0);
+    // 1/W^2 from the table entries 1/w^2 that follow the weights
+    const T iw2ab = idet ? wtab[P + ia] * wtab[P + ib] : T(0);
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       const int q = c * P2 + ab;
@@ -133,10 +134,9 @@ __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
       ft[c] = g02 * ur[c] + g12 * us[c] + g22 * ut[c];
       T wj;
       if (idet) {
-        const T W = wab * wtab[c];
         const T dG = g00 * (g11 * g22 - g12 * g12) - g01 * (g01 * g22 - g12 * g02) +
                      g02 * (g01 * g12 - g11 * g02);
-        wj = dG * id / (W * W);
+        wj = dG * (id * iw2ab) * wtab[P + c];
       } else {
         wj = WJ[e * P3 + q];
       }
@@ -518,6 +518,8 @@ void launch_apply(const mfsem_op& op, const T* x, T* y, double alpha, bool stiff
                   hipStream_t s, bool accumulate) {
   if (!accumulate) zero<T>(y, op.d.n_dof * op.d.batch, s);
   if (op.d.n_elem == 0) return;
+  // the GLL kernels read 1/w^2 right after the weights
+  if (op.off.iw2 != op.off.w + op.Q) fail(MFSEM_EDEVICE, "table layout: 1/w^2 must follow w");
   if (stiffness && launch_brick<T>(op, G_of<T>(op), WJ_of<T>(op),
                                    op.use_det ? idet_of<T>(op) : nullptr, tables_of<T>(op), x, y,
                                    (T)alpha, s))

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
   constexpr int p = C::p, P2 = C::P2, P3 = C::P3, NE = C::NE;
   constexpr int BX = C::BX, BY = C::BY, BZ = C::BZ, LX = C::LX, LY = C::LY, LN = C::LN;
   __shared__ T sD[P * P];
-  __shared__ T sw[P];
+  __shared__ T sw[2 * P];  // w, then 1/w^2 (they follow each other in the tables)
   __shared__ T xs[LN];
   __shared__ T ys[LN];
   __shared__ T F[NE * 2 * P3];
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
     if (idet) id = idet[(int64_t)bt * ne_tot + e];
   }
   for (int i = tid; i < P * P; i += C::THREADS) sD[i] = Dtab[i];
-  for (int i = tid; i < P; i += C::THREADS) sw[i] = wtab[i];
+  for (int i = tid; i < 2 * P; i += C::THREADS) sw[i] = wtab[i];
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int n = tid + it * C::THREADS;
@@ -242,6 +242,7 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
     dy[m] = sD[ib * P + m];
   }
   const T wab = sw[ia] * sw[ib];
+  const T iw2ab = sw[P + ia] * sw[P + ib];
 
   T u[P], ft[P], out[P];
   if (active) {
@@ -276,10 +277,10 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
       if constexpr (OTF) {
         wj = wjo;
       } else if (idet) {
-        const T W = wab * sw[c];
+        // W|J| = det G / (W^2 det sigma), with 1/W^2 from the table
         const T dG = g00 * (g11 * g22 - g12 * g12) - g01 * (g01 * g22 - g12 * g02) +
                      g02 * (g01 * g12 - g11 * g02);
-        wj = dG * id / (W * W);
+        wj = dG * (id * iw2ab) * sw[P + c];
       } else {
         wj = WJ[e * P3 + q];
       }

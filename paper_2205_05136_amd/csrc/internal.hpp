@@ -56,8 +56,9 @@ void lagrange_matrices(const std::vector<double>& nodes, const std::vector<doubl
 //   Bm [Q][Pm] : map basis at the quadrature points
 //   Dm [Q][Pm] : map basis derivative at the quadrature points
 //   w  [Q]     : 1D quadrature weights
+//   iw2 [Q]    : 1 / w^2 (the mass weight from det G needs 1/W^2, W = w_a w_b w_c)
 struct TableOffsets {
-  int B, Db, Dq, Bm, Dm, w, total;
+  int B, Db, Dq, Bm, Dm, w, iw2, total;
 };
 TableOffsets table_offsets(int P, int Q, int Pm);
 std::vector<double> build_tables(int p, int quad, int Q, int pm);

@@ -108,6 +108,7 @@ TableOffsets table_offsets(int P, int Q, int Pm) {
   o.Bm = at; at += Q * Pm;
   o.Dm = at; at += Q * Pm;
   o.w = at;  at += Q;
+  o.iw2 = at; at += Q;
   o.total = at;
   return o;
 }
@@ -128,6 +129,7 @@ std::vector<double> build_tables(int p, int quad, int Q, int pm) {
   lagrange_matrices(mnodes, pts, &L, &D);
   for (int i = 0; i < Q * Pm; ++i) { t[o.Bm + i] = L[i]; t[o.Dm + i] = D[i]; }
   for (int k = 0; k < Q; ++k) t[o.w + k] = w[k];
+  for (int k = 0; k < Q; ++k) t[o.iw2 + k] = 1.0 / (w[k] * w[k]);
   return t;
 }
 
