@@ -307,6 +307,26 @@ mfsem_status mfsem_ap_imex_rhs(int64_t n, double dt, double chi, double cm,
                                const double* i_stim, const double* mass_diag, double* b,
                                void* stream);
 
+/* The paper's BDF2 step of the partitioned scheme (Section 3, the ionic and
+ * monodomain discretization, with the extrapolation V* = 2 V^n - V^{n-1} and
+ * ionic current interpolation, lumped for SEM-NI), for the same model:
+ *   gating, implicit in w^{n+1}:
+ *     3 w^{n+1} - 4 w^n + w^{n-1} = (2 dt/t_scale) G(u*, w^{n+1}),
+ *     u* = (V* - v_rest)/v_amp  (solved in closed form: G is quadratic in w);
+ *   b = mass_diag * (chi*cm/dt * (4 V^n - V^{n-1})/2
+ *                    + chi*cm*(v_amp/t_scale) * F(u*, w^{n+1}) + i_stim),
+ * the right-hand side of (3/2 chi*cm/dt M + K) V^{n+1} = b; then
+ * w_old <- w^n and w <- w^{n+1}.  V = V^n (at time t), V_old = V^{n-1}.
+ * act (may be NULL): where act < 0 and V_old < v_act <= V, act is set to the
+ * crossing time interpolated linearly in [t - dt, t] (activation times).
+ * All arrays [device][n] FP64; i_stim may be NULL (zero).  A first step from
+ * rest may take V_old = V and w_old = w.                                     */
+mfsem_status mfsem_ap_bdf2_rhs(int64_t n, double dt, double chi, double cm,
+                               const mfsem_ap_params* prm, const double* V, const double* V_old,
+                               double* w, double* w_old, const double* i_stim,
+                               const double* mass_diag, double* b, double t, double v_act,
+                               double* act, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,3 +38,55 @@ def imex_rhs_and_gate(V, w, i_stim, mass_diag, dt, chi, cm, prm):
     b = mass_diag * (alpha * V + chi * cm * (prm["v_amp"] / prm["t_scale"]) * F + i_stim)
     w_next = w + (dt / prm["t_scale"]) * G
     return b, w_next
+
+
+# --- BDF2 partitioned scheme (Section 3, the ionic and monodomain discretization) ---
+#
+# Gating, implicit in w^{n+1} with the extrapolated potential V* = 2 V^n - V^{n-1}:
+#     (3 w^{n+1} - 4 w^n + w^{n-1}) / (2 dt) = G(u*, w^{n+1}) / t_scale
+# Potential: (3 alpha1/2 M + K) V^{n+1} = M (alpha1 (4 V^n - V^{n-1}) / 2
+#            + chi Cm (v_amp/t_scale) F(u*, w^{n+1}) + I_stim),  alpha1 = chi Cm / dt,
+# with the ionic current taken at (V*, w^{n+1}) (ionic current interpolation,
+# which for SEM-NI is the lumped form, so the right-hand side is pointwise).
+
+def bdf2_gate(u_star, w_n, w_nm1, dt, k, a, eps0, mu1, mu2, t_scale, iters=60, **_):
+    """w^{n+1} solving the scalar BDF2 gating equation at every DOF, by Newton's
+    method on R(w) = 3w - 4w^n + w^{n-1} - (2 dt / t_scale) G(u*, w), started at
+    the BDF1 predictor and run to convergence (R is quadratic in w)."""
+    h = 2.0 * dt / t_scale
+    w = np.array(w_n, dtype=np.float64, copy=True)
+    c = k * u_star * (u_star - a - 1.0)
+    r = mu1 / (u_star + mu2)
+    for _ in range(iters):
+        G = (eps0 + r * w) * (-w - c)
+        dG = r * (-w - c) - (eps0 + r * w)
+        R = 3.0 * w - 4.0 * w_n + w_nm1 - h * G
+        dR = 3.0 - h * dG
+        step = R / dR
+        w = w - step
+        if np.all(np.abs(step) <= 1e-16 * np.maximum(1.0, np.abs(w))):
+            break
+    return w
+
+
+def bdf2_rhs_and_gate(V, V_old, w, w_old, i_stim, mass_diag, dt, chi, cm, prm):
+    """Returns (b, w_next) of one BDF2 step: the gating update and the pointwise
+    right-hand side of (3/2 alpha1 M + K) V^{n+1} = b."""
+    V_star = 2.0 * V - V_old
+    u_star = (V_star - prm["v_rest"]) / prm["v_amp"]
+    w_next = bdf2_gate(u_star, w, w_old, dt, **prm)
+    F, _ = ap_rates(u_star, w_next, **prm)
+    alpha1 = chi * cm / dt
+    b = mass_diag * (alpha1 * (4.0 * V - V_old) / 2.0
+                     + chi * cm * (prm["v_amp"] / prm["t_scale"]) * F + i_stim)
+    return b, w_next
+
+
+def activation_update(act, V_old, V, t_old, t_new, v_act):
+    """First crossing of v_act by the potential at every DOF, linearly
+    interpolated in time between two steps; act < 0 marks 'not yet'."""
+    act = np.array(act, dtype=np.float64, copy=True)
+    for i in range(len(act)):
+        if act[i] < 0.0 and V_old[i] < v_act <= V[i]:
+            act[i] = t_old + (t_new - t_old) * (v_act - V_old[i]) / (V[i] - V_old[i])
+    return act

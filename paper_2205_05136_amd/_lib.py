@@ -98,6 +98,9 @@ PROTOTYPES = {
                         C.c_size_t, _P]),
     "mfsem_ap_imex_rhs": (_ST, [C.c_int64, C.c_double, C.c_double, C.c_double,
                                 C.POINTER(APParams), _P, _P, _P, _P, _P, _P]),
+    "mfsem_ap_bdf2_rhs": (_ST, [C.c_int64, C.c_double, C.c_double, C.c_double,
+                                C.POINTER(APParams), _P, _P, _P, _P, _P, _P, _P, C.c_double,
+                                C.c_double, _P, _P]),
 }
 
 _lib = None

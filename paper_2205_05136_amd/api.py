@@ -357,11 +357,40 @@ def pcg(op: Operator, b, x0=None, mg: Multigrid | None = None, rtol=1e-10, atol=
 
 
 # ------------------------------------------------------------------ ionic ---
+def _ap_params(params: dict):
+    return L.APParams(**{k: float(params[k]) for k in ("k", "a", "eps0", "mu1", "mu2", "v_rest",
+                                                       "v_amp", "t_scale")})
+
+
+def _pointwise(n, device, *arrays):
+    """The pointwise kernels index every array with the same n FP64 entries."""
+    for a in arrays:
+        if a is None:
+            continue
+        if not (a.dtype == torch.float64 and a.is_contiguous() and a.numel() == n
+                and a.device == device):
+            raise ValueError(f"expected contiguous float64 arrays of {n} entries on {device}")
+
+
 def ap_imex_rhs(V, w, mass_diag, dt, chi, cm, params: dict, i_stim=None, out=None):
     """b and the updated gate w for one IMEX step (mfsem_ap_imex_rhs)."""
     b = torch.empty_like(V) if out is None else out
-    prm = L.APParams(**{k: float(params[k]) for k in ("k", "a", "eps0", "mu1", "mu2", "v_rest",
-                                                      "v_amp", "t_scale")})
+    _pointwise(V.numel(), V.device, V, w, mass_diag, i_stim, b)
+    prm = _ap_params(params)
     L.check(L.load().mfsem_ap_imex_rhs(V.numel(), dt, chi, cm, C.byref(prm), _ptr(V), _ptr(w),
                                        _ptr(i_stim), _ptr(mass_diag), _ptr(b), _stream()))
+    return b
+
+
+def ap_bdf2_rhs(V, V_old, w, w_old, mass_diag, dt, chi, cm, params: dict, i_stim=None,
+                out=None, t=0.0, v_act=0.0, act=None):
+    """b of the BDF2 step; w_old <- w, w <- w^{n+1}; activation times in `act`
+    (mfsem_ap_bdf2_rhs)."""
+    b = torch.empty_like(V) if out is None else out
+    _pointwise(V.numel(), V.device, V, V_old, w, w_old, mass_diag, i_stim, b, act)
+    prm = _ap_params(params)
+    L.check(L.load().mfsem_ap_bdf2_rhs(V.numel(), dt, chi, cm, C.byref(prm), _ptr(V),
+                                       _ptr(V_old), _ptr(w), _ptr(w_old), _ptr(i_stim),
+                                       _ptr(mass_diag), _ptr(b), float(t), float(v_act),
+                                       _ptr(act), _stream()))
     return b

@@ -28,6 +28,10 @@ void launch_box_parents(const int32_t n[3], int32_t* parent, int8_t* child, hipS
 void launch_ap(int64_t n, double dt, double chi, double cm, const mfsem_ap_params& prm,
                const double* V, double* w, const double* istim, const double* m, double* b,
                hipStream_t s);
+void launch_ap_bdf2(int64_t n, double dt, double chi, double cm, const mfsem_ap_params& prm,
+                    const double* V, const double* Vo, double* w, double* wo, const double* istim,
+                    const double* m, double* b, double t, double v_act, double* act,
+                    hipStream_t s);
 
 namespace {
 
@@ -507,6 +511,23 @@ mfsem_status mfsem_ap_imex_rhs(int64_t n, double dt, double chi, double cm,
     require(prm->v_amp != 0.0 && prm->t_scale > 0.0, "v_amp != 0 and t_scale > 0 required");
     require(n == 0 || (V && w && mass_diag && b), "NULL array");
     launch_ap(n, dt, chi, cm, *prm, V, w, i_stim, mass_diag, b, as_stream(stream));
+  });
+}
+
+mfsem_status mfsem_ap_bdf2_rhs(int64_t n, double dt, double chi, double cm,
+                               const mfsem_ap_params* prm, const double* V, const double* V_old,
+                               double* w, double* w_old, const double* i_stim,
+                               const double* mass_diag, double* b, double t, double v_act,
+                               double* act, void* stream) {
+  return guarded([&] {
+    require(n >= 0, "n must be >= 0");
+    require(dt > 0.0 && chi > 0.0 && cm > 0.0, "dt, chi and cm must be positive");
+    require(prm != nullptr, "params is NULL");
+    require(prm->v_amp != 0.0 && prm->t_scale > 0.0, "v_amp != 0 and t_scale > 0 required");
+    require(n == 0 || (V && V_old && w && w_old && mass_diag && b), "NULL array");
+    require(std::isfinite(t) && std::isfinite(v_act), "t and v_act must be finite");
+    launch_ap_bdf2(n, dt, chi, cm, *prm, V, V_old, w, w_old, i_stim, mass_diag, b, t, v_act, act,
+                   as_stream(stream));
   });
 }
 

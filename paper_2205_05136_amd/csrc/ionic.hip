@@ -32,7 +32,60 @@ __global__ void ap_kernel(int64_t n, double dt, double chi, double cm, mfsem_ap_
   }
 }
 
+// BDF2 step of the partitioned scheme (Section 3: the ionic and monodomain
+// discretization), with the extrapolated potential V* = 2 V^n - V^{n-1}:
+//   gating:  3 w^{n+1} - 4 w^n + w^{n-1} = (2 dt/t_scale) G(u*, w^{n+1}),
+//            a quadratic in w^{n+1} (G is eps(u*, w) times a term linear in w):
+//            with c = k u*(u*-a-1), r = mu1/(u*+mu2), h = 2 dt/t_scale,
+//            h r w^2 + (3 + h (eps0 + r c)) w + (h eps0 c - 4 w^n + w^{n-1}) = 0,
+//            solved by the root that tends to the linear solution as r -> 0;
+//   b = m (chi cm/dt (4 V^n - V^{n-1})/2 + chi cm (v_amp/t_scale) F(u*, w^{n+1}) + I_stim),
+// then w^{n-1} <- w^n, w^n <- w^{n+1}.  With act != NULL, the first upward
+// crossing of v_act between V^{n-1} (at t - dt) and V^n (at t) is recorded by
+// linear interpolation where act < 0.
+__global__ void ap_bdf2_kernel(int64_t n, double dt, double chi, double cm, mfsem_ap_params prm,
+                               const double* __restrict__ V, const double* __restrict__ Vo,
+                               double* __restrict__ w, double* __restrict__ wo,
+                               const double* __restrict__ istim, const double* __restrict__ m,
+                               double* __restrict__ b, double t, double v_act,
+                               double* __restrict__ act) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double a1 = chi * cm / dt;
+  const double fscale = chi * cm * (prm.v_amp / prm.t_scale);
+  const double h = 2.0 * dt / prm.t_scale;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = V[i], vo = Vo[i];
+    const double us = (2.0 * v - vo - prm.v_rest) / prm.v_amp;
+    const double wn = w[i], wm = wo[i];
+    const double c = prm.k * us * (us - prm.a - 1.0);
+    const double r = prm.mu1 / (us + prm.mu2);
+    const double qa = h * r, qb = 3.0 + h * (prm.eps0 + r * c), qc = h * prm.eps0 * c - 4.0 * wn + wm;
+    // -2 qc / (qb + sqrt(qb^2 - 4 qa qc)) is the root continuous at qa = 0 (qb > 0)
+    const double disc = fmax(qb * qb - 4.0 * qa * qc, 0.0);
+    const double wnew = -2.0 * qc / (qb + sqrt(disc));
+    const double F = prm.k * us * (1.0 - us) * (us - prm.a) - us * wnew;
+    const double is = istim ? istim[i] : 0.0;
+    b[i] = m[i] * (a1 * 0.5 * (4.0 * v - vo) + fscale * F + is);
+    wo[i] = wn;
+    w[i] = wnew;
+    if (act && act[i] < 0.0 && vo < v_act && v >= v_act)
+      act[i] = (t - dt) + dt * (v_act - vo) / (v - vo);
+  }
+}
+
 }  // namespace
+
+void launch_ap_bdf2(int64_t n, double dt, double chi, double cm, const mfsem_ap_params& prm,
+                    const double* V, const double* Vo, double* w, double* wo, const double* istim,
+                    const double* m, double* b, double t, double v_act, double* act,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  ap_bdf2_kernel<<<(unsigned)blocks, 256, 0, s>>>(n, dt, chi, cm, prm, V, Vo, w, wo, istim, m, b,
+                                                  t, v_act, act);
+  MFSEM_LAUNCH("ap_bdf2_kernel");
+}
 
 void launch_ap(int64_t n, double dt, double chi, double cm, const mfsem_ap_params& prm,
                const double* V, double* w, const double* istim, const double* m, double* b,

@@ -1,9 +1,16 @@
 """Full monodomain time loop: the outer loop of Alg. 1 around the hot path.
 
-Per step (first-order IMEX; the paper's scheme is BDF2 with extrapolation,
-Section 3): the pointwise Aliev-Panfilov update and SEM-NI right-hand side
-(mfsem_ap_imex_rhs), then (alpha M + K) V^{n+1} = b by GMG-PCG warm-started from
-V^n (Section 5), alpha = chi Cm / dt.  All arithmetic runs in libmfsem.
+Two schemes, both a pointwise ionic update and SEM-NI right-hand side followed
+by one GMG-PCG solve warm-started from V^n (Section 5):
+  "imex1": first-order IMEX (mfsem_ap_imex_rhs), (alpha M + K) V^{n+1} = b with
+           alpha = chi Cm / dt;
+  "bdf2":  the paper's partitioned BDF2 scheme (Section 3) with the
+           extrapolation V* = 2 V^n - V^{n-1}, the gating equation implicit in
+           w^{n+1} and the ionic current at (V*, w^{n+1}) (mfsem_ap_bdf2_rhs),
+           (3/2 alpha M + K) V^{n+1} = b; the first step starts from rest
+           (V^{-1} = V^0, w^{-1} = w^0).  Activation times (the first upward
+           crossing of v_act, interpolated in time) are kept per DOF.
+All arithmetic runs in libmfsem.
 """
 from __future__ import annotations
 
@@ -33,8 +40,12 @@ class StepStats:
 class Monodomain:
     def __init__(self, spec, dt, chi, cm, ap_params: dict, stimulus: Stimulus,
                  coarsening=(("p", 2), ("p", 1)), degree=3, precision=torch.float32,
-                 rtol=1e-10, atol=0.0, device="cuda"):
-        self.spec = spec.with_(alpha=chi * cm / dt)
+                 rtol=1e-10, atol=0.0, device="cuda", scheme="imex1", v_act=-40.0):
+        if scheme not in ("imex1", "bdf2"):
+            raise ValueError("scheme must be 'imex1' or 'bdf2'")
+        self.scheme, self.v_act = scheme, float(v_act)
+        scale = 1.5 if scheme == "bdf2" else 1.0
+        self.spec = spec.with_(alpha=scale * chi * cm / dt)
         self.dt, self.chi, self.cm, self.prm = dt, chi, cm, ap_params
         self.rtol, self.atol = rtol, atol
         self.ops, self.mg = api.hierarchy(self.spec, coarsening=coarsening, degree=degree,
@@ -53,19 +64,31 @@ class Monodomain:
                             device=op.device)
         self.w = torch.zeros_like(self.V)
         self.b = torch.empty_like(self.V)
+        # BDF2 history (start from rest) and activation times (-1: not yet)
+        self.V_old = self.V.clone()
+        self.w_old = self.w.clone()
+        self.act = torch.full_like(self.V, -1.0)
         self.t = 0.0
         self.stats = StepStats()
 
     def step(self):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev[0].record()
-        stim = self.i_stim if self.t < self.stim.duration else None
-        api.ap_imex_rhs(self.V, self.w, self.mass, self.dt, self.chi, self.cm, self.prm,
-                        i_stim=stim, out=self.b)
+        if self.scheme == "imex1":
+            stim = self.i_stim if self.t < self.stim.duration else None
+            api.ap_imex_rhs(self.V, self.w, self.mass, self.dt, self.chi, self.cm, self.prm,
+                            i_stim=stim, out=self.b)
+        else:
+            # the applied current at t^{n+1}; activation crossings in [t - dt, t]
+            stim = self.i_stim if self.t + self.dt <= self.stim.duration else None
+            api.ap_bdf2_rhs(self.V, self.V_old, self.w, self.w_old, self.mass, self.dt, self.chi,
+                            self.cm, self.prm, i_stim=stim, out=self.b, t=self.t,
+                            v_act=self.v_act, act=self.act)
         ev[1].record()
         V, info = api.pcg(self.op, self.b, x0=self.V, mg=self.mg, rtol=self.rtol, atol=self.atol,
                           max_it=500)
         ev[2].record()
+        self.V_old = self.V
         self.V = V
         self.t += self.dt
         torch.cuda.synchronize()

@@ -346,6 +346,32 @@ def test_ionic_step():
     assert rel_l2(to_np(wd), w_ref) <= 1e-14
 
 
+def test_ionic_bdf2_step():
+    announce("ionic bdf2 step")
+    n = 5000
+    # half the points near the activation threshold, so that crossings occur
+    V = np.where(np.arange(n) % 2 == 0, synth.uniform(13, n, -85.0, 30.0),
+                 synth.uniform(20, n, -46.0, -34.0))
+    Vo = V + synth.uniform(14, n, -3.0, 3.0)
+    w = synth.uniform(15, n, 0.0, 1.5)
+    wo = w + synth.uniform(16, n, -0.05, 0.05)
+    ist = synth.uniform(17, n, 0.0, 50.0)
+    m = synth.uniform(18, n, 0.1, 1.0)
+    dt, t, v_act = 0.05, 3.0, -40.0
+    b_ref, w_ref = oion.bdf2_rhs_and_gate(V, Vo, w, wo, ist, m, dt, synth.CHI, synth.CM,
+                                          synth.AP_PARAMS)
+    act0 = np.where(synth.uniform(19, n) > 0.5, -1.0, 1.25)
+    act_ref = oion.activation_update(act0, Vo, V, t - dt, t, v_act)
+    wd, wod, actd = to_dev(w), to_dev(wo), to_dev(act0)
+    b = mf.ap_bdf2_rhs(to_dev(V), to_dev(Vo), wd, wod, to_dev(m), dt, synth.CHI, synth.CM,
+                       synth.AP_PARAMS, i_stim=to_dev(ist), t=t, v_act=v_act, act=actd)
+    assert rel_l2(to_np(b), b_ref) <= 1e-14
+    assert rel_l2(to_np(wd), w_ref) <= 1e-14
+    assert np.array_equal(to_np(wod), w)  # w_old <- w^n
+    assert np.allclose(to_np(actd), act_ref, rtol=1e-13, atol=0)
+    assert (act_ref > 1.25).sum() > 20  # crossings were recorded
+
+
 # ------------------------------------------------------------------ errors ---
 def test_error_paths():
     announce("error paths")

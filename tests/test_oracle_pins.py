@@ -490,3 +490,87 @@ def test_aliev_panfilov_rest_and_rates():
                                     synth.CHI, synth.CM, prm)
     assert abs(b[0] - 2.0 * (synth.CHI * synth.CM / 0.05) * prm["v_rest"]) < 1e-12
     assert wn[0] == 0.0
+
+
+# --- BDF2 partitioned scheme (Section 3) ----------------------------------------
+
+def _cell_rates(V, w, prm):
+    """Single-cell AP model in mV and ms: dV/dt, dw/dt (no diffusion, no stimulus)."""
+    u = (V - prm["v_rest"]) / prm["v_amp"]
+    F, G = ionic.ap_rates(np.atleast_1d(u), np.atleast_1d(w), **prm)
+    return (prm["v_amp"] / prm["t_scale"]) * F[0], G[0] / prm["t_scale"]
+
+
+def _cell_run(scheme, dt, T, V0, w0, Vm1, wm1, prm):
+    """March one cell (M = 1, K = 0) with the oracle's step functions."""
+    chi, cm = synth.CHI, synth.CM
+    one, zero = np.ones(1), np.zeros(1)
+    V, w, Vo, wo = np.array([V0]), np.array([w0]), np.array([Vm1]), np.array([wm1])
+    for _ in range(int(round(T / dt))):
+        if scheme == "bdf2":
+            b, wn = ionic.bdf2_rhs_and_gate(V, Vo, w, wo, zero, one, dt, chi, cm, prm)
+            Vn = b / (1.5 * chi * cm / dt)
+        else:
+            b, wn = ionic.imex_rhs_and_gate(V, w, zero, one, dt, chi, cm, prm)
+            Vn = b / (chi * cm / dt)
+        Vo, wo, V, w = V, w, Vn, wn
+    return V[0], w[0]
+
+
+def test_bdf2_cell_converges_at_second_order():
+    """The partitioned BDF2 step with the extrapolated potential is second-order
+    accurate (Section 3); the first-order IMEX step first-order.  Reference: an
+    adaptive Runge-Kutta solve of the same cell ODE at tight tolerance."""
+    from scipy.integrate import solve_ivp
+    prm = synth.AP_PARAMS
+    y0 = (-30.0, 0.4)
+    T = 1.0
+    rhs = lambda t, y: list(_cell_rates(y[0], y[1], prm))
+    ref = solve_ivp(rhs, (0.0, T), y0, method="DOP853", rtol=1e-13, atol=1e-13,
+                    dense_output=True)
+    VT = ref.sol(T)[0]
+    err = {}
+    for scheme in ("bdf2", "imex1"):
+        err[scheme] = []
+        for dt in (0.02, 0.01, 0.005):
+            # exact history value at t = -dt for the two-step scheme
+            back = solve_ivp(rhs, (0.0, -dt), y0, method="DOP853", rtol=1e-13, atol=1e-13)
+            Vm1, wm1 = back.y[0, -1], back.y[1, -1]
+            VTn, _ = _cell_run(scheme, dt, T, y0[0], y0[1], Vm1, wm1, prm)
+            err[scheme].append(abs(VTn - VT))
+    r2 = [np.log2(err["bdf2"][i] / err["bdf2"][i + 1]) for i in range(2)]
+    r1 = [np.log2(err["imex1"][i] / err["imex1"][i + 1]) for i in range(2)]
+    assert all(1.8 < r < 2.3 for r in r2), (err, r2)
+    assert all(0.8 < r < 1.3 for r in r1), (err, r1)
+
+
+def test_bdf2_gate_linear_case_and_rest_state():
+    """With mu1 = 0 the gating equation is linear: w = (4 w^n - w^{n-1} - h eps0 c) /
+    (3 + h eps0); the rest state is a fixed point of the whole step."""
+    prm = dict(synth.AP_PARAMS, mu1=0.0)
+    rng = np.random.default_rng(3)
+    u = rng.uniform(-0.1, 1.1, 50)
+    wn, wm = rng.uniform(0, 2, 50), rng.uniform(0, 2, 50)
+    dt = 0.05
+    h = 2 * dt / prm["t_scale"]
+    c = prm["k"] * u * (u - prm["a"] - 1.0)
+    w_closed = (4 * wn - wm - h * prm["eps0"] * c) / (3 + h * prm["eps0"])
+    w = ionic.bdf2_gate(u, wn, wm, dt, **prm)
+    assert np.max(np.abs(w - w_closed)) < 1e-14
+    prm = synth.AP_PARAMS
+    V = np.full(3, prm["v_rest"])
+    b, wnext = ionic.bdf2_rhs_and_gate(V, V, np.zeros(3), np.zeros(3), np.zeros(3),
+                                       np.full(3, 2.0), dt, synth.CHI, synth.CM, prm)
+    assert np.all(wnext == 0.0)
+    # (3/2 alpha1 M + K) V = b is solved by V = v_rest (K annihilates constants)
+    assert np.allclose(b, 2.0 * 1.5 * synth.CHI * synth.CM / dt * prm["v_rest"], rtol=1e-15)
+
+
+def test_activation_time_interpolation():
+    """A linear ramp V(t) = -100 + 10 t crosses -40 mV at t = 6 exactly."""
+    t = np.arange(0.0, 10.01, 0.3)
+    V = -100.0 + 10.0 * t
+    act = np.full(1, -1.0)
+    for n in range(1, len(t)):
+        act = ionic.activation_update(act, V[n - 1:n], V[n:n + 1], t[n - 1], t[n], -40.0)
+    assert abs(act[0] - 6.0) < 1e-12
