@@ -322,7 +322,8 @@ def main():
                    "quadrature": spec.quad, "nq1d": spec.q, "alpha": spec.alpha,
                    "sigma_mS_per_mm": list(spec.sigma),
                    "multigrid": "p " + "->".join([str(spec.p)] + [str(c[1]) for c in coarsening])
-                                + ", Chebyshev degree 3 on [0.08, 1.2]*lambda_max (10 CG steps)",
+                                + ", Chebyshev degree 3 on [0.08, 1.2]*lambda_max (10 CG steps),"
+                                + " coarsest level Chebyshev degree 2",
                    "parallelism": "single GPU"},
         "apply": {"reps_per_step": R, "fp64_ms": round(t_apply, 5), "fp64_kernel_ms": round(t_kernel, 5),
                   "fp64_kernel_gdofs": round(NB / (t_kernel * 1e-3) / 1e9, 3),
