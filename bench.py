@@ -169,6 +169,46 @@ def cpu_baseline(spec, budget_s=20.0):
                        f"{os.cpu_count()} logical CPUs")}
 
 
+def matrix_based(mf, op, x, t_mf_ms, spec, max_bytes=40e9):
+    """The paper's matrix-based comparison on the GPU: assemble A in CSR
+    (mfsem_csr_assemble) and time its product (mfsem_csr_spmv) beside the
+    matrix-free kernel, outside the timed steps.  Skipped when the matrix would
+    exceed max_bytes."""
+    import ctypes
+    import torch
+    from paper_2205_05136_amd import _lib as L
+    nnz = ctypes.c_int64()
+    L.check(L.load().mfsem_csr_nnz(op.handle, ctypes.byref(nnz)))
+    nbytes = 12 * nnz.value + 8 * (spec.n_dof + 1)
+    if nbytes > max_bytes:
+        return {"skipped": f"{nbytes / 1e9:.1f} GB matrix"}
+    E = lambda: torch.cuda.Event(enable_timing=True)
+    a, b = E(), E()
+    a.record()
+    A = mf.CsrMatrix(op)
+    b.record()
+    torch.cuda.synchronize()
+    t_asm = a.elapsed_time(b)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        A.apply(x, out=y)
+    R = 20
+    a.record()
+    for _ in range(R):
+        A.apply(x, out=y)
+    b.record()
+    torch.cuda.synchronize()
+    t_spmv = a.elapsed_time(b) / R
+    moved = 12 * nnz.value + 8 * (spec.n_dof + 1) + 16 * spec.n_dof  # vals, cols, row_ptr, x, y
+    out = {"nnz": nnz.value, "matrix_bytes": nbytes, "assemble_ms": round(t_asm, 3),
+           "spmv_ms": round(t_spmv, 4), "spmv_gdofs": round(spec.n_dof / (t_spmv * 1e-3) / 1e9, 3),
+           "spmv_hbm_frac": round(moved / (t_spmv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "matrix_free_speedup": round(t_spmv / t_mf_ms, 2)}
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +218,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--no-matrix-based", action="store_true",
+                    help="skip the assembled-matrix (CSR) comparison")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run an elementwise copy of 2 x N doubles (HBM counter reference)")
     args = ap.parse_args()
@@ -372,6 +414,8 @@ def main():
                              "pcg_iters_mean": round(sum(its) / k, 3),
                              "V_range_mV": [round(float(sim.V.min()), 3), round(float(sim.V.max()), 3)],
                              "sim_time_ms": round(sim.t, 4), "setup_s": round(t_setup, 3)}
+    if kind == "pcg" and not args.no_matrix_based:
+        out["matrix_based"] = matrix_based(mf, op, x, t_kernel, spec)
     if args.copy_ref:
         # y = x + 0: reads 8N and writes 8N bytes; its counter readings calibrate
         # the FETCH_SIZE / WRITE_SIZE of the operator kernel

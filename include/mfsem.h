@@ -211,6 +211,28 @@ mfsem_status mfsem_op_grad_sigma(const mfsem_op* op, const double* u, const doub
                                  double* g, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Matrix-based path: A assembled as a sparse matrix (the paper's matrix-based
+ * comparison: the global matrix from the element matrices, Alg. 2, and sparse
+ * matrix-vector products, Section 4), for operators on a structured lattice
+ * with GLL quadrature, batch 1 and FP64 geometry (EUNSUPPORTED otherwise).
+ * CSR with the element-connectivity pattern: row g holds, in increasing
+ * column order, every node of every element containing node g (up to
+ * (2p+1)^3), explicit zeros included; alpha is the operator's at assembly.  */
+
+/* Number of stored entries. [host] */
+mfsem_status mfsem_csr_nnz(const mfsem_op* op, int64_t* nnz);
+
+/* Fill row_ptr [n_dof+1] (int64), col [nnz] (int32) and val [nnz] (FP64),
+ * all [device] and caller-sized from mfsem_csr_nnz.                         */
+mfsem_status mfsem_csr_assemble(const mfsem_op* op, int64_t* row_ptr, int32_t* col, double* val,
+                                void* stream);
+
+/* y = A x with a CSR matrix (one wavefront per row); x, y [device][n_rows]
+ * FP64, not aliased.                                                         */
+mfsem_status mfsem_csr_spmv(int64_t n_rows, const int64_t* row_ptr, const int32_t* col,
+                            const double* val, const double* x, double* y, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Geometric multigrid V-cycle (Section 4.3).  Levels are operators created by
  * the caller, finest first; transfers[l] links level l (fine) and l+1.
  * P-transfers keep the elements and lower the degree; H-transfers map each

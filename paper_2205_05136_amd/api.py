@@ -207,6 +207,31 @@ class Operator:
         self.sigma = s.reshape(self.batch, self.n_elem, 3)
 
 
+# ----------------------------------------------------------- matrix-based ---
+class CsrMatrix:
+    """The operator assembled as a CSR matrix (mfsem_csr_*): the matrix-based
+    path the paper compares the matrix-free one with."""
+
+    def __init__(self, op: Operator):
+        lib = L.load()
+        nnz = C.c_int64()
+        L.check(lib.mfsem_csr_nnz(op.handle, C.byref(nnz)))
+        self.n, self.nnz, self.device = op.n_dof, nnz.value, op.device
+        self.row_ptr = torch.empty(self.n + 1, dtype=torch.int64, device=op.device)
+        self.col = torch.empty(self.nnz, dtype=torch.int32, device=op.device)
+        self.val = torch.empty(self.nnz, dtype=torch.float64, device=op.device)
+        L.check(lib.mfsem_csr_assemble(op.handle, _ptr(self.row_ptr), _ptr(self.col),
+                                       _ptr(self.val), _stream()))
+
+    def apply(self, x, out=None):
+        """y = A x (mfsem_csr_spmv)."""
+        y = torch.empty_like(x) if out is None else out
+        _pointwise(self.n, self.device, x, y)
+        L.check(L.load().mfsem_csr_spmv(self.n, _ptr(self.row_ptr), _ptr(self.col),
+                                        _ptr(self.val), _ptr(x), _ptr(y), _stream()))
+        return y
+
+
 # -------------------------------------------------------------- multigrid ---
 class Multigrid:
     """V-cycle preconditioner over a list of level operators (mfsem_mg_*).

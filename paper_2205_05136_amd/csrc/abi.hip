@@ -354,6 +354,43 @@ mfsem_status mfsem_op_grad_sigma(const mfsem_op* op, const double* u, const doub
   });
 }
 
+// ----------------------------------------------------------- matrix-based ---
+namespace {
+void check_csr_op(const mfsem_op* op) {
+  require(op != nullptr, "operator is NULL");
+  if (!op->structured || op->d.quad != MFSEM_GLL || op->d.batch != 1 || op->G64 == nullptr)
+    fail(MFSEM_EUNSUPPORTED,
+         "the assembled matrix needs a structured GLL lattice, batch 1 and FP64 geometry");
+}
+}  // namespace
+
+mfsem_status mfsem_csr_nnz(const mfsem_op* op, int64_t* nnz) {
+  return guarded([&] {
+    check_csr_op(op);
+    require(nnz != nullptr, "NULL argument");
+    *nnz = csr_nnz(*op);
+  });
+}
+
+mfsem_status mfsem_csr_assemble(const mfsem_op* op, int64_t* row_ptr, int32_t* col, double* val,
+                                void* stream) {
+  return guarded([&] {
+    check_csr_op(op);
+    require(row_ptr && col && val, "NULL argument");
+    csr_assemble(*op, row_ptr, col, val, as_stream(stream));
+  });
+}
+
+mfsem_status mfsem_csr_spmv(int64_t n_rows, const int64_t* row_ptr, const int32_t* col,
+                            const double* val, const double* x, double* y, void* stream) {
+  return guarded([&] {
+    require(n_rows >= 0, "n_rows must be >= 0");
+    require(n_rows == 0 || (row_ptr && col && val && x && y), "NULL argument");
+    require(x != y, "x and y must not alias");
+    csr_spmv(n_rows, row_ptr, col, val, x, y, as_stream(stream));
+  });
+}
+
 // -------------------------------------------------------------- multigrid ---
 namespace {
 

@@ -1,0 +1,202 @@
+// Matrix-based path: the assembled sparse matrix of A = alpha M + K in CSR and
+// its product with a vector (the paper's matrix-based comparison: the global
+// matrix assembled from the element matrices, Alg. 2, then sparse
+// matrix-vector products inside CG, Section 4).
+//
+// Structured lattices only.  The pattern is the element connectivity: node
+// (I, J, K) couples to every node of every element containing it, i.e. along
+// each axis to [lo, hi] with
+//     lo = I - (I mod p), hi = lo + p                  (I inside an element)
+//     lo = max(I - p, 0), hi = min(I + p, N - 1)       (I on an element face)
+// so a row holds rx * ry * rz entries (up to (2p+1)^3), in increasing global
+// index.  Row offsets follow in closed form from the 1D prefix sums of r.
+// Entries that vanish for GLL collocation (i and j in different rows of all
+// three axes) stay in the pattern as zeros, as in a standard assembly of full
+// element matrices.
+#include "internal.hpp"
+
+namespace mfsem {
+
+namespace {
+
+struct Axis {
+  int p;
+  int64_t N;  // nodes along the axis
+};
+
+__host__ __device__ inline void axis_range(const Axis& a, int64_t I, int64_t& lo, int64_t& r) {
+  if (I % a.p == 0) {
+    lo = I - a.p > 0 ? I - a.p : 0;
+    const int64_t hi = I + a.p < a.N - 1 ? I + a.p : a.N - 1;
+    r = hi - lo + 1;
+  } else {
+    lo = I - I % a.p;
+    r = a.p + 1;
+  }
+}
+
+// sum of the row extents r(I') over I' < I (0 <= I <= N): interior nodes
+// have p + 1, the two end nodes p + 1, the other multiples of p 2p + 1
+__host__ __device__ inline int64_t axis_prefix(const Axis& a, int64_t I) {
+  const int64_t m = (I + a.p - 1) / a.p;  // multiples of p in [0, I)
+  const int64_t ends = (I > 0 ? 1 : 0) + (I > a.N - 1 ? 1 : 0);
+  return (I - m) * (a.p + 1) + (m - ends) * (2 * a.p + 1) + ends * (a.p + 1);
+}
+
+struct Lattice {
+  Axis x, y, z;
+  int64_t Tx, Ty;  // axis_prefix(N) of x and y
+};
+
+__host__ __device__ inline int64_t row_start(const Lattice& L, int64_t I, int64_t J, int64_t K) {
+  int64_t lo, ry, rz;
+  axis_range(L.y, J, lo, ry);
+  axis_range(L.z, K, lo, rz);
+  return axis_prefix(L.z, K) * L.Tx * L.Ty +
+         rz * (axis_prefix(L.y, J) * L.Tx + ry * axis_prefix(L.x, I));
+}
+
+constexpr int CT = 256;  // threads per block; one wave of 64 lanes per row
+
+__global__ __launch_bounds__(CT) void csr_pattern_kernel(Lattice L, int64_t n_rows,
+                                                         int64_t* __restrict__ row_ptr,
+                                                         int32_t* __restrict__ col) {
+  const int lane = threadIdx.x & 63;
+  const int64_t NX = L.x.N, NY = L.y.N;
+  for (int64_t g = ((int64_t)blockIdx.x * CT + threadIdx.x) >> 6; g < n_rows;
+       g += ((int64_t)gridDim.x * CT) >> 6) {
+    const int64_t I = g % NX, J = (g / NX) % NY, K = g / (NX * NY);
+    int64_t lx, rx, ly, ry, lz, rz;
+    axis_range(L.x, I, lx, rx);
+    axis_range(L.y, J, ly, ry);
+    axis_range(L.z, K, lz, rz);
+    const int64_t start = row_start(L, I, J, K);
+    if (lane == 0) {
+      row_ptr[g] = start;
+      if (g == n_rows - 1) row_ptr[n_rows] = start + rx * ry * rz;
+    }
+    for (int64_t t = lane; t < rx * ry * rz; t += 64) {
+      const int64_t ic = lx + t % rx, jc = ly + (t / rx) % ry, kc = lz + t / (rx * ry);
+      col[start + t] = (int32_t)(ic + NX * (jc + NY * kc));
+    }
+  }
+}
+
+// One workgroup per element: every entry (i, j) of the element matrix
+//   A_e[i][j] = alpha W|J|_i delta_ij + sum_q grad phi_i(q)^T G_q grad phi_j(q)
+// from the stored G (GLL points = nodes, so grad phi_i is non-zero only at the
+// points in the three lines through node i), added into the row of node i.
+__global__ __launch_bounds__(CT) void csr_values_kernel(Lattice L, int P, const double* __restrict__ G,
+                                                        const double* __restrict__ WJ, double alpha,
+                                                        const double* __restrict__ Db,
+                                                        int nex, int ney, double* __restrict__ val) {
+  __shared__ double sD[(MFSEM_MAX_P + 1) * (MFSEM_MAX_P + 1)];
+  const int64_t e = blockIdx.x;
+  const int p = P - 1, P2 = P * P, P3 = P2 * P;
+  for (int i = threadIdx.x; i < P2; i += CT) sD[i] = Db[i];
+  __syncthreads();
+  const int64_t ex = e % nex, ey = (e / nex) % ney, ez = e / ((int64_t)nex * ney);
+  const double* Ge = G + e * P3 * 6;
+  const int64_t NX = L.x.N, NY = L.y.N;
+  auto Gc = [&](int qa, int qb, int qc, int comp) { return Ge[(qa + P * (qb + P * qc)) * 6 + comp]; };
+  auto D = [&](int q, int m) { return sD[q * P + m]; };  // l_m'(x_q)
+  for (int t = threadIdx.x; t < P3 * P3; t += CT) {
+    const int i = t / P3, j = t % P3;
+    const int ia = i % P, ib = (i / P) % P, ic = i / P2;
+    const int ja = j % P, jb = (j / P) % P, jc = j / P2;
+    const bool sa = ia == ja, sb = ib == jb, sc = ic == jc;
+    if (!sa && !sb && !sc) continue;  // no common line: structurally zero
+    double v = 0.0;
+    if (sb && sc)
+      for (int a = 0; a < P; ++a) v += D(a, ia) * D(a, ja) * Gc(a, ib, ic, 0);
+    if (sa && sc)
+      for (int b = 0; b < P; ++b) v += D(b, ib) * D(b, jb) * Gc(ia, b, ic, 3);
+    if (sa && sb)
+      for (int c = 0; c < P; ++c) v += D(c, ic) * D(c, jc) * Gc(ia, ib, c, 5);
+    if (sc) {  // x-y couplings
+      v += D(ja, ia) * D(ib, jb) * Gc(ja, ib, ic, 1);
+      v += D(jb, ib) * D(ia, ja) * Gc(ia, jb, ic, 1);
+    }
+    if (sb) {  // x-z couplings
+      v += D(ja, ia) * D(ic, jc) * Gc(ja, ib, ic, 2);
+      v += D(jc, ic) * D(ia, ja) * Gc(ia, ib, jc, 2);
+    }
+    if (sa) {  // y-z couplings
+      v += D(jb, ib) * D(ic, jc) * Gc(ia, jb, ic, 4);
+      v += D(jc, ic) * D(ib, jb) * Gc(ia, ib, jc, 4);
+    }
+    if (i == j) v += alpha * WJ[e * P3 + i];
+    // global node of i (row) and j (column), and the column's slot in the row
+    const int64_t I = ex * p + ia, J = ey * p + ib, K = ez * p + ic;
+    const int64_t Ic = ex * p + ja, Jc = ey * p + jb, Kc = ez * p + jc;
+    int64_t lx, rx, ly, ry, lz, rz;
+    axis_range(L.x, I, lx, rx);
+    axis_range(L.y, J, ly, ry);
+    axis_range(L.z, K, lz, rz);
+    const int64_t pos = row_start(L, I, J, K) + ((Kc - lz) * ry + (Jc - ly)) * rx + (Ic - lx);
+    (void)NX;
+    (void)NY;
+    atomic_add(&val[pos], v);
+  }
+}
+
+__global__ __launch_bounds__(CT) void csr_spmv_kernel(int64_t n_rows, const int64_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ val,
+                                                      const double* __restrict__ x,
+                                                      double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t g = ((int64_t)blockIdx.x * CT + threadIdx.x) >> 6; g < n_rows;
+       g += ((int64_t)gridDim.x * CT) >> 6) {
+    const int64_t a = row_ptr[g], b = row_ptr[g + 1];
+    double s = 0.0;
+    for (int64_t k = a + lane; k < b; k += 64) s += val[k] * x[col[k]];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) y[g] = s;
+  }
+}
+
+Lattice lattice_of(const mfsem_op& op) {
+  const int p = op.d.p;
+  Lattice L;
+  L.x = Axis{p, (int64_t)p * op.lat[0] + 1};
+  L.y = Axis{p, (int64_t)p * op.lat[1] + 1};
+  L.z = Axis{p, (int64_t)p * op.lat[2] + 1};
+  L.Tx = axis_prefix(L.x, L.x.N);
+  L.Ty = axis_prefix(L.y, L.y.N);
+  return L;
+}
+
+unsigned row_blocks(int64_t rows) {
+  int64_t b = (rows * 64 + CT - 1) / CT;
+  if (b > 65536) b = 65536;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+int64_t csr_nnz(const mfsem_op& op) {
+  const Lattice L = lattice_of(op);
+  return L.Tx * L.Ty * axis_prefix(L.z, L.z.N);
+}
+
+void csr_assemble(const mfsem_op& op, int64_t* row_ptr, int32_t* col, double* val, hipStream_t s) {
+  const Lattice L = lattice_of(op);
+  const int64_t n = op.d.n_dof, nnz = csr_nnz(op);
+  csr_pattern_kernel<<<row_blocks(n), CT, 0, s>>>(L, n, row_ptr, col);
+  MFSEM_LAUNCH("csr_pattern_kernel");
+  vfill<double>(val, nnz, 0.0, s);
+  if (op.d.n_elem == 0) return;
+  csr_values_kernel<<<(unsigned)op.d.n_elem, CT, 0, s>>>(
+      L, op.P, op.G64, op.WJ64, op.alpha, op.tab64 + op.off.Db, op.lat[0], op.lat[1], val);
+  MFSEM_LAUNCH("csr_values_kernel");
+}
+
+void csr_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+              const double* x, double* y, hipStream_t s) {
+  if (n <= 0) return;
+  csr_spmv_kernel<<<row_blocks(n), CT, 0, s>>>(n, row_ptr, col, val, x, y);
+  MFSEM_LAUNCH("csr_spmv_kernel");
+}
+
+}  // namespace mfsem

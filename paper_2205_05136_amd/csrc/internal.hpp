@@ -155,6 +155,11 @@ bool launch_brick(const mfsem_op& op, const T* G, const T* WJ, const T* idet, co
 void launch_lattice_check(const mfsem_op& op, unsigned long long* bad, hipStream_t s);
 void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, double* g,
                        hipStream_t s);
+// matrix-based path on structured lattices (csr.hip)
+int64_t csr_nnz(const mfsem_op& op);
+void csr_assemble(const mfsem_op& op, int64_t* row_ptr, int32_t* col, double* val, hipStream_t s);
+void csr_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+              const double* x, double* y, hipStream_t s);
 
 // vector kernels (vec.hip)
 template <typename T>

@@ -130,6 +130,32 @@ def test_apply_large_bricks(p, n):
             assert np.max(np.abs(got - ref)) <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 6, 8])
+def test_assembled_matrix(p):
+    """The matrix-based path: the CSR matrix assembled on the GPU equals the
+    oracle's assembly of the element matrices, and its product the matrix-free
+    apply."""
+    import scipy.sparse as sp
+    announce(f"csr p{p}")
+    spec = _spec(p, (3, 2, 2) if p <= 5 else (2, 2, 1))
+    prob, A, M, K = oracle_problem(spec, sigma_seed=5)
+    op, _ = _op(spec, sigma=to_dev(prob.sigma))
+    csr = mf.CsrMatrix(op)
+    rp, col, val = csr.row_ptr.cpu().numpy(), csr.col.cpu().numpy().astype(np.int64), to_np(csr.val)
+    assert rp[0] == 0 and rp[-1] == csr.nnz == len(col)
+    # row extents along each axis of the element-connectivity pattern
+    P = p + 1
+    counts = [np.array([P if i % p else (2 * p + 1 if 0 < i < p * n else p + 1)
+                        for i in range(p * n + 1)]) for n in spec.n]
+    expect = np.einsum("k,j,i->kji", counts[2], counts[1], counts[0]).reshape(-1)
+    assert np.array_equal(np.diff(rp), expect)
+    assert all(np.all(np.diff(col[rp[r]:rp[r + 1]]) > 0) for r in range(0, spec.n_dof, 7))
+    Ag = sp.csr_matrix((val, col, rp), shape=A.shape)
+    assert abs(Ag - A).max() <= 1e-13 * abs(A).max()
+    x = synth.uniform(104, spec.n_dof)
+    assert rel_l2(to_np(csr.apply(to_dev(x))), A @ x) <= TOL64
+
+
 @pytest.mark.parametrize("p,quad,q", [(2, "gll", 0), (4, "gll", 0), (7, "gll", 0), (4, "gauss", 6)])
 def test_apply_f32(p, quad, q):
     announce(f"apply f32 p{p} {quad}")
