@@ -18,6 +18,8 @@ estimates) is outside the timed region, as in the paper.
 Other workloads (--workload):
   slab-p{2..7}[-gauss]  the sheared slab refined to about 51M DOFs (p-sweep),
   c3 / c3-gauss         128 x 48 x 24 hexes at p = 7, SEM-NI / SEM (q = 9),
+  c2-p{1..8}            the c2 slab at another degree (the matrix-based comparison
+                        per degree),
   c4                    32^3 box at p = 4 with a batch of 8 per-element
                         conductivity sets: the step's solve is a forward
                         GMG-PCG plus the adjoint gradient dL/dsigma,
@@ -108,6 +110,10 @@ def workload(name):
     import synth
     if name == "c2":
         return synth.C2, "c2: sheared slab 20x7x3 mm, 40x14x6 hexes, p=4, SEM-NI (GLL), rotating fibers"
+    if name.startswith("c2-p"):
+        p = int(name[4:])
+        spec = synth.slab(p, (40, 14, 6))
+        return spec, f"the c2 slab (40x14x6 hexes) at p={p}, SEM-NI (GLL)"
     if name.startswith("slab-p"):
         parts = name.split("-")
         p = int(parts[1][1:])
