@@ -130,6 +130,26 @@ def test_apply_large_bricks(p, n):
             assert np.max(np.abs(got - ref)) <= 1e-12 * np.abs(ref).max()
 
 
+# Degenerate shapes: a single element, and meshes one element thick in two
+# directions (every brick ragged), at every degree.
+EDGE_CASES = [(p, n) for p in (1, 2, 4, 5, 7, 8) for n in ((1, 1, 1), (9, 1, 1), (1, 5, 3))]
+
+
+@pytest.mark.parametrize("p,n", EDGE_CASES, ids=[f"p{c[0]}-{c[1][0]}x{c[1][1]}x{c[1][2]}"
+                                                   for c in EDGE_CASES])
+def test_apply_degenerate_meshes(p, n):
+    announce(f"apply degenerate p{p} {n}")
+    spec = synth.slab(p, n)
+    prob, A, M, K = oracle_problem(spec)
+    x = synth.uniform(105, spec.n_dof)
+    for kw in (dict(), dict(structured=False)):
+        op, _ = _op(spec, store_f32=True, **kw)
+        assert rel_l2(to_np(op.apply(to_dev(x))), A @ x) <= TOL64, kw
+        assert rel_l2(to_np(op.apply(to_dev(x, torch.float32))), A @ x) <= TOL32, kw
+        z = op.apply(torch.zeros(spec.n_dof, dtype=torch.float64, device="cuda"))
+        assert float(z.abs().max()) == 0.0
+
+
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 6, 8])
 def test_assembled_matrix(p):
     """The matrix-based path: the CSR matrix assembled on the GPU equals the

@@ -163,6 +163,28 @@ def test_monodomain_bdf2_matches_oracle():
     assert np.max(np.abs(a[act >= 0] - act[act >= 0])) <= 1e-6
 
 
+@pytest.mark.parametrize("p", [2, 4])
+def test_full_size_properties(p):
+    """At the 51M-DOF p-sweep size, properties that hold at any size: K
+    annihilates constants (alpha = 0), A is symmetric (x^T A y = y^T A x), and
+    1^T M 1 is the slab's volume 20 x 7 x 3 mm^3 (the shear keeps it)."""
+    announce(f"full-size properties p{p}")
+    spec = synth.sweep(p)
+    op = mf.Operator.from_spec(spec, alpha=0.0)
+    one = torch.ones(spec.n_dof, dtype=torch.float64, device="cuda")
+    k1 = op.apply(one)
+    g = torch.arange(spec.n_dof, device="cuda", dtype=torch.float64)
+    x, y = torch.sin(0.37 * g), torch.cos(0.11 * g + 0.5)
+    ax = op.apply(x)
+    assert float(k1.abs().max()) <= 1e-12 * float(ax.abs().max())
+    op.set_alpha(spec.alpha)
+    ax, ay = op.apply(x), op.apply(y)
+    xay, yax = float(torch.dot(x, ay)), float(torch.dot(y, ax))
+    assert abs(xay - yax) <= 1e-12 * (float(torch.dot(x.abs(), ay.abs())) + 1.0)
+    vol = float(op.apply_mass(one).sum())
+    assert abs(vol - 420.0) <= 1e-9 * 420.0
+
+
 @pytest.mark.parametrize("name", ["slab-p7-51M", "slab-p4-gauss-51M"])
 def test_full_size_sampled_rows(name):
     """At the 51M-DOF workload size, in the benchmark's launch configuration:
