@@ -50,18 +50,18 @@ def log(*a):
 
 def apply_kernel(spec):
     """The kernel that performs y += A x for this workload, its source file, and
-    the model of the bytes one launch must move (one read of x, one read and one
-    write of y, the 6 stored G entries per quadrature point, plus per kernel:
-    1/det(sigma) per element for the GLL kernels, whose mass weight W|J| is
-    recovered from det G; W|J| per point and the element-to-node index for the
-    Gauss kernel; the index for the general GLL kernel, while the structured
-    lattice kernel computes node numbers)."""
+    the model of the bytes one launch must move: one read of x, one read and one
+    write of y, the 6 stored G entries per quadrature point and 1/det(sigma) per
+    element (the mass weight W|J| is recovered from det G, so no W|J| is read),
+    plus the element-to-node index for the Gauss kernel (the lattice kernel
+    computes node numbers)."""
     P = spec.p + 1
     if spec.quad == "gll":
         return (f"ax_brick_kernel<double,{P}>", "ax_brick.hip",
                 "8*(x + y read + y write)*N + 48*n_elem*q^3 (G) + 8*n_elem (1/det sigma)")
     return (f"ax_sem_kernel<double,{P},{spec.q}>", "ax.hip",
-            "8*(x + y read + y write)*N + 56*n_elem*q^3 (G, W|J|) + 4*n_elem*(p+1)^3 (index)")
+            "8*(x + y read + y write)*N + 48*n_elem*q^3 (G) + 8*n_elem (1/det sigma) "
+            "+ 4*n_elem*(p+1)^3 (index)")
 
 
 def algorithmic_bytes(spec, n_elem, n_dof, w, quad):
@@ -71,7 +71,7 @@ def algorithmic_bytes(spec, n_elem, n_dof, w, quad):
     g = 6 * n_elem * q3 * w
     if quad == "gll":
         return 3 * w * n_dof + g + w * n_elem
-    return 3 * w * n_dof + w * n_elem * q3 + g + 4 * n_elem * P3
+    return 3 * w * n_dof + g + w * n_elem + 4 * n_elem * P3
 
 
 def algorithmic_flops(spec, n_elem, n_dof, quad):

@@ -180,8 +180,9 @@ struct SemCfg {
 template <typename T, int P, int Q, bool STIFF>
 __global__ __launch_bounds__((SemCfg<P, Q>::THREADS)) void ax_sem_kernel(
     int64_t n_elem, int64_t n_dof, const int32_t* __restrict__ ed, const T* __restrict__ G,
-    const T* __restrict__ WJ, T alpha, const T* __restrict__ Btab, const T* __restrict__ Dqtab,
-    const T* __restrict__ x, T* __restrict__ y) {
+    const T* __restrict__ WJ, const T* __restrict__ idet, T alpha, const T* __restrict__ Btab,
+    const T* __restrict__ Dqtab, const T* __restrict__ wtab, const T* __restrict__ x,
+    T* __restrict__ y) {
   using C = SemCfg<P, Q>;
   constexpr int P2 = C::P2, P3 = C::P3, Q2 = C::Q2, Q3 = C::Q3, NE = C::NE;
   __shared__ T sB[Q * P];
@@ -274,6 +275,10 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS)) void ax_sem_kernel(
     T fz[Q];
     if (active) {
       const T* Ge = G + ((int64_t)bt * n_elem + e) * 6 * Q3;
+      // mass weight W|J| = det G / (W^2 det sigma) when det sigma > 0 (no W|J|
+      // stream; wtab holds w and then 1/w^2), else the stored W|J|
+      const T id = idet ? idet[(int64_t)bt * n_elem + e] : T(0);
+      const T iw2ij = idet ? wtab[Q + i] * wtab[Q + j] : T(0);
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         const int q = k * Q2 + j * Q + i;
@@ -284,7 +289,15 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS)) void ax_sem_kernel(
         b3[q] = g00 * dx[k] + g01 * dy[k] + g02 * dz[k];
         b2[q] = g01 * dx[k] + g11 * dy[k] + g12 * dz[k];
         fz[k] = g02 * dx[k] + g12 * dy[k] + g22 * dz[k];
-        rq[k] = (alpha != T(0)) ? alpha * WJ[e * Q3 + q] * uq[k] : T(0);
+        T wj;
+        if (idet) {
+          const T dG = g00 * (g11 * g22 - g12 * g12) - g01 * (g01 * g22 - g12 * g02) +
+                       g02 * (g01 * g12 - g11 * g02);
+          wj = dG * (id * iw2ij) * wtab[Q + k];
+        } else {
+          wj = WJ[e * Q3 + q];
+        }
+        rq[k] = alpha * wj * uq[k];
       }
     }
     __syncthreads();
@@ -401,8 +414,9 @@ void run_sem(const mfsem_op& op, const T* x, T* y, T alpha, hipStream_t s) {
   const unsigned nb = blocks_for(op.d.n_elem, C::NE);
   const T* tab = tables_of<T>(op);
   ax_sem_kernel<T, P, Q, STIFF><<<dim3(nb, op.d.batch), dim3(C::THREADS), 0, s>>>(
-      op.d.n_elem, op.d.n_dof, op.d.elem_dof, G_of<T>(op), WJ_of<T>(op), alpha, tab + op.off.B,
-      tab + op.off.Dq, x, y);
+      op.d.n_elem, op.d.n_dof, op.d.elem_dof, G_of<T>(op), WJ_of<T>(op),
+      op.use_det ? idet_of<T>(op) : nullptr, alpha, tab + op.off.B, tab + op.off.Dq,
+      tab + op.off.w, x, y);
   MFSEM_LAUNCH("ax_sem_kernel");
 }
 
