@@ -141,8 +141,12 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
   constexpr int BX = C::BX, BY = C::BY, BZ = C::BZ, LX = C::LX, LY = C::LY, LN = C::LN;
   __shared__ T sD[P * P];
   __shared__ T sw[2 * P];  // w, then 1/w^2 (they follow each other in the tables)
+  // FP32 sums the elements' contributions to a lattice node by gathering them
+  // from the flux buffer (no LDS atomics: the FP32 kernel is bound by LDS
+  // instructions, 6-15% faster); FP64 adds into an LDS lattice (faster there)
+  constexpr bool GATHER = sizeof(T) == sizeof(float);
   __shared__ T xs[LN];
-  __shared__ T ys[LN];
+  __shared__ T ys[GATHER ? 1 : LN];
   __shared__ T F[NE * 2 * P3];
   __shared__ T cs[OTF ? 3 * LN : 1];  // OTF: lattice coordinates [3][LN]
 
@@ -224,7 +228,7 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
     const int n = tid + it * C::THREADS;
     if (n < LN) {
       xs[n] = xv[it];
-      ys[n] = 0;
+      if constexpr (!GATHER) ys[n] = 0;
       if constexpr (OTF) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) cs[r * LN + n] = cv[3 * it + r];
@@ -305,10 +309,19 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
         v += dyt[m] * Fe[P3 + c * P2 + m * P + ia];
         v += Dtab[m * P + c] * ft[m];
       }
-      lds_add(&ys[o + LX * LY * c], v);
+      if constexpr (GATHER) out[c] = v;
+      else lds_add(&ys[o + LX * LY * c], v);
     }
   }
   __syncthreads();
+  if constexpr (GATHER) {
+    // each element's node results into the first half of its (consumed) flux space
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < P; ++c) Fe[c * P2 + ab] = out[c];
+    }
+    __syncthreads();
+  }
   // 5. write back: every lattice node of the brick is added to y through the L2
   // atomic unit (y holds zero or the sum being accumulated into).  Plain stores
   // of the nodes no other brick touches, interleaved on the same cache lines
@@ -316,7 +329,33 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
   for (int n = tid; n < LN; n += blockDim.x) {
     const int i = n % LX, j = (n / LX) % LY, k = n / (LX * LY);
     if (i > nex * p || j > ney * p || k > nez * p) continue;
-    atomic_add(y + (I0 + i) + NX * ((J0 + j) + NY * (K0 + k)), ys[n]);
+    T sum;
+    if constexpr (GATHER) {
+      // the node's contributions: one element per axis inside an element, two
+      // on a face between elements of the brick (up to 8 in all)
+      sum = 0;
+      const int xi = i / p, yj = j / p, zk = k / p;
+#pragma unroll
+      for (int dz = 0; dz < 2; ++dz) {
+        const int ez = zk - dz;
+        if (ez < 0 || ez >= nez || (dz == 1 && k % p != 0)) continue;
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+          const int ey = yj - dy;
+          if (ey < 0 || ey >= ney || (dy == 1 && j % p != 0)) continue;
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            const int ex = xi - dx;
+            if (ex < 0 || ex >= nex || (dx == 1 && i % p != 0)) continue;
+            sum += F[(ex + BX * (ey + BY * ez)) * 2 * P3 + (k - ez * p) * P2 + (j - ey * p) * P +
+                     (i - ex * p)];
+          }
+        }
+      }
+    } else {
+      sum = ys[n];
+    }
+    atomic_add(y + (I0 + i) + NX * ((J0 + j) + NY * (K0 + k)), sum);
   }
 }
 
