@@ -237,11 +237,9 @@ class Multigrid:
     """V-cycle preconditioner over a list of level operators (mfsem_mg_*).
 
     transfers[l] = ("p",) or ("h", parent, child) links level l and l+1.
-    coarse_degree: Chebyshev steps on the coarsest level (default 2; with the
-    mass term of the time-stepping operator the coarsest levels are well
-    conditioned, and 1 to 8 steps gave the same PCG iteration counts)."""
+    coarse_degree: Chebyshev steps on the coarsest level (default 2 * degree)."""
 
-    def __init__(self, ops, transfers, degree=3, coarse_degree=2, lo=0.08, hi=1.2,
+    def __init__(self, ops, transfers, degree=3, coarse_degree=None, lo=0.08, hi=1.2,
                  eig_iters=10, seed=12345, lambda_max=None, precision=torch.float64):
         lib = L.load()
         self.ops = list(ops)
@@ -266,7 +264,7 @@ class Multigrid:
             lam = (C.c_double * len(vals))(*vals)
         self.precision = precision
         self.desc = L.MgDesc(n_levels=nl, ops=self._ops_arr, transfers=trs, degree=degree,
-                             coarse_degree=coarse_degree, lo_frac=lo, hi_frac=hi,
+                             coarse_degree=coarse_degree or 2 * degree, lo_frac=lo, hi_frac=hi,
                              eig_iters=eig_iters, eig_seed=seed, lambda_max=lam,
                              precision=L.MFSEM_F64 if precision == torch.float64 else L.MFSEM_F32)
         nbytes = C.c_size_t()
