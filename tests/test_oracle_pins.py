@@ -191,6 +191,24 @@ def test_dirichlet_energy_of_linear_functions():
     assert abs(u @ (K @ u) - 0.3 * (c @ c) * 420.0) < 1e-9 * 0.3 * (c @ c) * 420.0
 
 
+@pytest.mark.parametrize("quad,q", [("gll", 0), ("gauss", 5)])
+def test_anisotropic_energy_of_linear_functions(quad, q):
+    """With a uniform fiber f (theta0 = theta1), sigma = sigma_t I + (sigma_l -
+    sigma_t) f f^T is constant and u = c.x gives u^T K u = c^T sigma c |Omega|
+    exactly (here on the sheared slab): pins the fiber term of the tensor."""
+    th = 0.7
+    sl, st = 0.17, 0.019
+    spec = _slab_small(3, quad, q).with_(theta0=th, theta1=th, sigma=(sl, st, st))
+    prob = operator.Problem(spec)
+    _, _, K = prob.assemble()
+    f = np.array([math.cos(th), math.sin(th), 0.0])
+    sigma = st * np.eye(3) + (sl - st) * np.outer(f, f)
+    for c in (np.array([0.3, -1.2, 0.7]), np.array([1.0, 0.0, 0.0])):
+        u = prob.mesh.xyz @ c
+        ref = (c @ sigma @ c) * 420.0
+        assert abs(u @ (K @ u) - ref) < 1e-10 * ref
+
+
 def _rotation(a, b, c):
     Rz = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
     Ry = np.array([[math.cos(b), 0, math.sin(b)], [0, 1, 0], [-math.sin(b), 0, math.cos(b)]])
