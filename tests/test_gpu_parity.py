@@ -320,7 +320,7 @@ def test_cg_c1():
     x_ref = spla.spsolve(A.tocsc(), f)
     assert rel_l2(to_np(x), x_ref) <= TOL64
     assert info.status == [0]
-    # the BASELINE tolerance 1e-10 from x0 = 0
+    # the benchmark's relative tolerance 1e-10 from x0 = 0
     x10, info10 = mf.pcg(op, to_dev(f), rtol=1e-10, max_it=500)
     r = f - A @ to_np(x10)
     assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(f)
