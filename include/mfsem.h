@@ -260,6 +260,11 @@ typedef struct {
   uint64_t eig_seed;
   const double* lambda_max;              /* [host] [n_levels][batch] or NULL = estimate */
   int32_t precision;                     /* mfsem_dtype of the whole cycle */
+  int32_t graphs;                        /* 1: the first cycle with a given (r, z) pair (and
+                                            levels' alpha) is captured into a HIP graph on a
+                                            private stream, later ones replay it with one
+                                            graph launch on `stream` (up to 4 pairs kept);
+                                            0: plain launches                              */
 } mfsem_mg_desc;
 
 mfsem_status mfsem_mg_workspace_bytes(const mfsem_mg_desc* d, size_t* bytes);

@@ -51,7 +51,8 @@ class MgDesc(C.Structure):
                 ("transfers", C.POINTER(TransferDesc)), ("degree", C.c_int32),
                 ("coarse_degree", C.c_int32), ("lo_frac", C.c_double), ("hi_frac", C.c_double),
                 ("eig_iters", C.c_int32), ("eig_seed", C.c_uint64),
-                ("lambda_max", C.POINTER(C.c_double)), ("precision", C.c_int32)]
+                ("lambda_max", C.POINTER(C.c_double)), ("precision", C.c_int32),
+                ("graphs", C.c_int32)]
 
 
 class SolveOpts(C.Structure):

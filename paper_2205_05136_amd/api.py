@@ -237,10 +237,14 @@ class Multigrid:
     """V-cycle preconditioner over a list of level operators (mfsem_mg_*).
 
     transfers[l] = ("p",) or ("h", parent, child) links level l and l+1.
-    coarse_degree: Chebyshev steps on the coarsest level (default 2 * degree)."""
+    coarse_degree: Chebyshev steps on the coarsest level (default 2 * degree).
+    graphs: replay each (r, z) pair's V-cycle as one captured HIP graph (off by
+    default: on MI355X the cycle is bound by the kernels, not by their launches,
+    and replays measured the same as plain launches)."""
 
     def __init__(self, ops, transfers, degree=3, coarse_degree=None, lo=0.08, hi=1.2,
-                 eig_iters=10, seed=12345, lambda_max=None, precision=torch.float64):
+                 eig_iters=10, seed=12345, lambda_max=None, precision=torch.float64,
+                 graphs=False):
         lib = L.load()
         self.ops = list(ops)
         self.batch = self.ops[0].batch
@@ -266,7 +270,8 @@ class Multigrid:
         self.desc = L.MgDesc(n_levels=nl, ops=self._ops_arr, transfers=trs, degree=degree,
                              coarse_degree=coarse_degree or 2 * degree, lo_frac=lo, hi_frac=hi,
                              eig_iters=eig_iters, eig_seed=seed, lambda_max=lam,
-                             precision=L.MFSEM_F64 if precision == torch.float64 else L.MFSEM_F32)
+                             precision=L.MFSEM_F64 if precision == torch.float64 else L.MFSEM_F32,
+                             graphs=int(graphs))
         nbytes = C.c_size_t()
         L.check(lib.mfsem_mg_workspace_bytes(C.byref(self.desc), C.byref(nbytes)))
         self.ws = _workspace(nbytes.value, self.ops[0].device)

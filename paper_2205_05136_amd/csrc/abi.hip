@@ -403,6 +403,7 @@ void mg_init(mfsem_mg& mg, const mfsem_mg_desc* d) {
   require(d->lo_frac > 0.0 && d->hi_frac > d->lo_frac, "need 0 < lo_frac < hi_frac");
   require(d->eig_iters >= 1 || d->lambda_max, "eig_iters must be >= 1");
   require(d->precision == MFSEM_F64 || d->precision == MFSEM_F32, "precision must be F64 or F32");
+  require(d->graphs == 0 || d->graphs == 1, "graphs must be 0 or 1");
   mg.d = *d;
   mg.prec = d->precision;
   mg.batch = d->ops[0] ? d->ops[0]->d.batch : 1;

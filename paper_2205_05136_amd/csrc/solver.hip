@@ -226,6 +226,15 @@ void vcycle(const mfsem_mg& mg, int l, T* b, T* x, hipStream_t s) {
 
 }  // namespace
 
+}  // namespace mfsem
+
+mfsem_mg::~mfsem_mg() {
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+  if (capture) (void)hipStreamDestroy(capture);
+}
+
+namespace mfsem {
+
 void mg_layout(mfsem_mg& mg, Arena& a) {
   const size_t w = mg.prec == MFSEM_F64 ? sizeof(double) : sizeof(float);
   const int B = mg.batch;
@@ -329,11 +338,51 @@ void mg_transfer(const mfsem_mg& mg, int level, int direction, const void* in, v
     transfer_t<float>(mg, level, direction, static_cast<const float*>(in), static_cast<float*>(out), s);
 }
 
-void mg_vcycle(const mfsem_mg& mg, const void* r, void* z, hipStream_t s) {
+namespace {
+void vcycle_launches(const mfsem_mg& mg, const void* r, void* z, hipStream_t s) {
   // r is only read: the finest level never clears its b
   void* b = const_cast<void*>(r);
   if (mg.prec == MFSEM_F64) vcycle<double>(mg, 0, static_cast<double*>(b), static_cast<double*>(z), s);
   else vcycle<float>(mg, 0, static_cast<float*>(b), static_cast<float*>(z), s);
+}
+constexpr size_t MAX_GRAPHS = 4;
+}  // namespace
+
+void mg_vcycle(const mfsem_mg& mg, const void* r, void* z, hipStream_t s) {
+  if (!mg.d.graphs) {
+    vcycle_launches(mg, r, z, s);
+    return;
+  }
+  std::vector<double> alpha(mg.lv.size());
+  for (size_t l = 0; l < mg.lv.size(); ++l) alpha[l] = mg.lv[l].op->alpha;
+  for (const auto& g : mg.graphs)
+    if (g.r == r && g.z == z && g.alpha == alpha) {
+      MFSEM_HIP(hipGraphLaunch(g.exec, s));
+      return;
+    }
+  // capture the launches on a private stream (the caller's may be the null
+  // stream, which cannot be captured); nothing runs until the replay below
+  if (!mg.capture) MFSEM_HIP(hipStreamCreateWithFlags(&mg.capture, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  MFSEM_HIP(hipStreamBeginCapture(mg.capture, hipStreamCaptureModeThreadLocal));
+  try {
+    vcycle_launches(mg, r, z, mg.capture);
+  } catch (...) {
+    (void)hipStreamEndCapture(mg.capture, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  MFSEM_HIP(hipStreamEndCapture(mg.capture, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  MFSEM_HIP(e);
+  if (mg.graphs.size() >= MAX_GRAPHS) {
+    (void)hipGraphExecDestroy(mg.graphs.front().exec);
+    mg.graphs.erase(mg.graphs.begin());
+  }
+  mg.graphs.push_back({r, z, alpha, exec});
+  MFSEM_HIP(hipGraphLaunch(exec, s));
 }
 
 // ------------------------------------------------------------------ PCG ---

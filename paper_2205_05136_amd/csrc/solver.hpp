@@ -28,6 +28,17 @@ struct mfsem_mg {
   int prec = MFSEM_F64;
   std::vector<mfsem_mg_level> lv;
   double* scratch = nullptr;   // reductions and coefficients during set-up
+  // with d.graphs: the V-cycle's launches captured once per (r, z) pair and the
+  // levels' alpha (a kernel argument), then replayed as one graph launch
+  struct Graph {
+    const void* r;
+    void* z;
+    std::vector<double> alpha;
+    hipGraphExec_t exec;
+  };
+  mutable std::vector<Graph> graphs;
+  mutable hipStream_t capture = nullptr;  // private stream the captures run on
+  ~mfsem_mg();
 };
 
 namespace mfsem {

@@ -42,7 +42,7 @@ def test_struct_layouts_match_header(tmp_path):
                     'sizeof(mfsem_box_desc), sizeof(mfsem_op_desc), sizeof(mfsem_mg_desc),'
                     'sizeof(mfsem_transfer_desc), sizeof(mfsem_solve_opts), sizeof(mfsem_solve_info),'
                     'sizeof(mfsem_ap_params), offsetof(mfsem_op_desc, alpha),'
-                    'offsetof(mfsem_op_desc, geometry), offsetof(mfsem_mg_desc, precision));'
+                    'offsetof(mfsem_op_desc, geometry), offsetof(mfsem_mg_desc, graphs));'
                     'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
@@ -52,7 +52,7 @@ def test_struct_layouts_match_header(tmp_path):
     want = [C.sizeof(L.BoxDesc), C.sizeof(L.OpDesc), C.sizeof(L.MgDesc),
             C.sizeof(L.TransferDesc), C.sizeof(L.SolveOpts), C.sizeof(L.SolveInfo),
             C.sizeof(L.APParams), L.OpDesc.alpha.offset, L.OpDesc.geometry.offset,
-            L.MgDesc.precision.offset]
+            L.MgDesc.graphs.offset]
     assert got == want
 
 

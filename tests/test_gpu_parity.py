@@ -296,6 +296,34 @@ def test_vcycle_matches_oracle(name):
     assert rel_l2(to_np(mg.vcycle(to_dev(b))), z_ref) <= TOL64
 
 
+@pytest.mark.parametrize("prec", [torch.float64, torch.float32])
+def test_vcycle_graph_replays_match_launches(prec):
+    """V-cycles replayed from captured HIP graphs equal plain launches: several
+    replays with other work and synchronisations between them, two (r, z) pairs,
+    and a change of alpha on the levels (which must be captured anew)."""
+    announce(f"vcycle graphs {prec}")
+    spec, chain = CHAINS["p4-2-1"]
+    ops, mg_g = mf.hierarchy(spec, coarsening=chain, degree=3, precision=prec)
+    mg_e = mf.Multigrid(ops, mg_g.transfers, degree=3, precision=prec, graphs=False,
+                        lambda_max=mg_g.lambdas().reshape(-1))
+    mg_g = mf.Multigrid(ops, mg_g.transfers, degree=3, precision=prec, graphs=True,
+                        lambda_max=mg_g.lambdas().reshape(-1))
+    tol = 1e-13 if prec == torch.float64 else 1e-6
+    rs = [to_dev(synth.uniform(600 + i, spec.n_dof), prec) for i in range(3)]
+    zs = [torch.empty_like(rs[0]) for _ in range(2)]
+    for rep in range(4):
+        for k, r in enumerate(rs):
+            z = zs[k % 2]
+            mg_g.vcycle(r, out=z)
+            ze = mg_e.vcycle(r)
+            torch.cuda.synchronize()
+            assert rel_l2(to_np(z), to_np(ze)) <= tol, (rep, k)
+            ops[0].apply(to_dev(synth.uniform(700 + rep, spec.n_dof)))  # other work between
+        if rep == 2:
+            for op in ops:
+                op.set_alpha(0.5 * op.alpha)
+
+
 def test_lambda_estimate_bounds():
     announce("lambda estimate")
     spec, chain = CHAINS["p4-2-1"]
