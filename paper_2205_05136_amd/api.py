@@ -294,8 +294,15 @@ class Multigrid:
         L.check(L.load().mfsem_mg_vcycle(self.handle, _ptr(r), _ptr(z), _stream()))
         return z
 
+    def _check_vec(self, v, level):
+        if v.dtype != self.precision or not v.is_cuda or not v.is_contiguous():
+            raise ValueError(f"expected a contiguous {self.precision} CUDA tensor")
+        if v.numel() != self.batch * self.ops[level].n_dof:
+            raise ValueError(f"expected {self.batch} x {self.ops[level].n_dof} values")
+
     def prolong(self, level, xc):
         """Fine-level vector P xc (mfsem_mg_transfer, direction 0)."""
+        self._check_vec(xc, level + 1)
         xf = torch.empty((self.batch, self.ops[level].n_dof) if self.batch > 1 else
                          (self.ops[level].n_dof,), dtype=xc.dtype, device=xc.device)
         L.check(L.load().mfsem_mg_transfer(self.handle, level, 0, _ptr(xc), _ptr(xf), _stream()))
@@ -303,6 +310,7 @@ class Multigrid:
 
     def restrict(self, level, rf):
         """Coarse-level vector P^T rf (mfsem_mg_transfer, direction 1)."""
+        self._check_vec(rf, level)
         rc = torch.empty((self.batch, self.ops[level + 1].n_dof) if self.batch > 1 else
                          (self.ops[level + 1].n_dof,), dtype=rf.dtype, device=rf.device)
         L.check(L.load().mfsem_mg_transfer(self.handle, level, 1, _ptr(rf), _ptr(rc), _stream()))
@@ -316,15 +324,17 @@ class Multigrid:
 
 
 def hierarchy(spec, fine_box: Box | None = None, coarsening=(("p", 2), ("p", 1)),
-              precision=torch.float64, device="cuda", sigma=None, xyz=None, **mg_kw):
+              precision=torch.float64, device="cuda", sigma=None, xyz=None, structured=True,
+              **mg_kw):
     """Operators and multigrid for a synth.BoxSpec.
 
     coarsening: sequence of ("p", degree) and ("h",) steps from the finest level.
     p-levels keep the geometry map of the level they coarsen; h-levels build the
-    octree-coarser box from the same recipe."""
+    octree-coarser box from the same recipe.  structured=False builds every
+    level as a general mesh (element kernels and element transfers)."""
     fine_box = fine_box or Box.from_spec(spec, device=device)
     store = dict(store_f64=True, store_f32=(precision == torch.float32))
-    kw = dict(sigma_const=spec.sigma, alpha=spec.alpha, sigma=sigma)
+    kw = dict(sigma_const=spec.sigma, alpha=spec.alpha, sigma=sigma, structured=structured)
     ops = [Operator(fine_box, quad=spec.quad, nq1d=spec.q if spec.quad == "gauss" else 0,
                     xyz=xyz, **store, **kw)]
     boxes = [fine_box]

@@ -19,7 +19,7 @@ OUT = os.path.join(PKG, "libmfsem.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["abi.hip", "tables.hip", "geom.hip", "ax.hip", "ax_brick.hip", "csr.hip", "vec.hip",
-           "transfer.hip", "solver.hip", "grad.hip", "ionic.hip", "mesh.hip"]
+           "transfer.hip", "transfer_lattice.hip", "solver.hip", "grad.hip", "ionic.hip", "mesh.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

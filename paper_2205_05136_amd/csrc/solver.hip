@@ -216,11 +216,17 @@ void vcycle(const mfsem_mg& mg, int l, T* b, T* x, hipStream_t s) {
   smooth<T>(mg, L, b, x, true, false, s);
   T* t = P_<T>(L.t);
   launch_apply<T>(*L.op, x, t, L.op->alpha, true, s, true);
-  const TransferArgs<T> ta = transfer_args<T>(mg, l);
-  launch_restrict<T>(ta, B, b, t, P_<T>(L.wmult), P_<T>(C.b), s);
-  vcycle<T>(mg, l + 1, P_<T>(C.b), P_<T>(C.x), s);
-  launch_prolong<T>(ta, B, P_<T>(C.x), t, s);  // overwrites t
-  vaxpy<T>(x, t, L.n * B, true, s);
+  if (L.lattice) {
+    lattice_restrict<T>(L.lt, B, b, t, P_<T>(C.b), s);  // overwrites C.b
+    vcycle<T>(mg, l + 1, P_<T>(C.b), P_<T>(C.x), s);
+    lattice_prolong<T>(L.lt, B, P_<T>(C.x), x, true, t, s);  // x += P xc, t = 0
+  } else {
+    const TransferArgs<T> ta = transfer_args<T>(mg, l);
+    launch_restrict<T>(ta, B, b, t, P_<T>(L.wmult), P_<T>(C.b), s);
+    vcycle<T>(mg, l + 1, P_<T>(C.b), P_<T>(C.x), s);
+    launch_prolong<T>(ta, B, P_<T>(C.x), t, s);  // overwrites t
+    vaxpy<T>(x, t, L.n * B, true, s);
+  }
   smooth<T>(mg, L, b, x, false, own_b, s);
 }
 
@@ -250,9 +256,15 @@ void mg_layout(mfsem_mg& mg, Arena& a) {
     L.x = a.take(nb * std::max(w, sizeof(double)));
     L.coef = a.take_n<double>((size_t)std::max(1, L.steps) * B * 2);
     if (l + 1 < mg.lv.size()) {
-      L.wmult = a.take(L.n * w);
-      const int Pf = L.op->P, Pc = mg.lv[l + 1].op->P;
-      L.I = a.take((size_t)2 * Pf * Pc * w);
+      const mfsem_op& C = *mg.lv[l + 1].op;
+      L.lattice = lattice_transfer_applies(*L.op, C, L.tr.kind);
+      if (L.lattice) lattice_transfer_layout(L.lt, *L.op, C, L.tr.kind, B, w, a);
+      // h-levels keep the element transfer's buffers: set-up falls back to it
+      // when the parent/child arrays do not follow the box convention
+      if (!L.lattice || L.tr.kind == MFSEM_TRANSFER_H) {
+        L.wmult = a.take(L.n * w);
+        L.I = a.take((size_t)2 * L.op->P * C.P * w);
+      }
     }
     scratch = std::max(scratch, (size_t)(4 * B + 2 * (size_t)dot_blocks(L.n) * B));
   }
@@ -271,7 +283,19 @@ void mg_setup(mfsem_mg& mg, hipStream_t s) {
       launch_diag<float>(*L.op, P_<float>(L.dinv), s);
       vinvert<float>(P_<float>(L.dinv), L.n * B, s);
     }
-    if (l + 1 < mg.lv.size()) {
+    if (l + 1 < mg.lv.size() && L.lattice && L.tr.kind == MFSEM_TRANSFER_H) {
+      auto* mismatch = reinterpret_cast<unsigned long long*>(mg.scratch);
+      MFSEM_HIP(hipMemsetAsync(mismatch, 0, sizeof(unsigned long long), s));
+      launch_box_parents_check(L.op->lat, L.tr.parent, L.tr.child, mismatch, s);
+      unsigned long long bad = 0;
+      MFSEM_HIP(hipMemcpyAsync(&bad, mismatch, sizeof(bad), hipMemcpyDeviceToHost, s));
+      MFSEM_HIP(hipStreamSynchronize(s));
+      L.lattice = bad == 0;
+    }
+    if (l + 1 < mg.lv.size() && L.lattice) {
+      MFSEM_HIP(hipStreamSynchronize(s));
+      lattice_transfer_upload(L.lt);
+    } else if (l + 1 < mg.lv.size()) {
       const mfsem_op& F = *L.op;
       const int P3 = F.P * F.P * F.P;
       if (f64) launch_inv_multiplicity<double>(F.d.elem_dof, F.d.n_elem, P3, L.n, P_<double>(L.wmult), s);
@@ -321,6 +345,11 @@ void mg_setup(mfsem_mg& mg, hipStream_t s) {
 
 template <typename T>
 void transfer_t(const mfsem_mg& mg, int l, int direction, const T* in, T* out, hipStream_t s) {
+  if (mg.lv[l].lattice) {
+    if (direction == 0) lattice_prolong<T>(mg.lv[l].lt, mg.batch, in, out, false, nullptr, s);
+    else lattice_restrict<T>(mg.lv[l].lt, mg.batch, in, nullptr, out, s);
+    return;
+  }
   const TransferArgs<T> ta = transfer_args<T>(mg, l);
   if (direction == 0) {
     launch_prolong<T>(ta, mg.batch, in, out, s);

@@ -3,7 +3,7 @@
 
 #include <vector>
 
-#include "transfer.hpp"
+#include "transfer_lattice.hpp"
 
 struct mfsem_mg_level {
   const mfsem_op* op = nullptr;
@@ -17,9 +17,12 @@ struct mfsem_mg_level {
   double* coef = nullptr;      // [steps][batch][2]
   std::vector<double> lam;     // [batch]
   // transfer to the next coarser level
-  void* wmult = nullptr;       // [n] 1/multiplicity
-  void* I = nullptr;           // [2][Pf][Pc]
+  void* wmult = nullptr;       // [n] 1/multiplicity (element transfers)
+  void* I = nullptr;           // [2][Pf][Pc] (element transfers)
   mfsem_transfer_desc tr{};
+  // both levels structured lattices: the transfers run as 1D lattice passes
+  bool lattice = false;
+  mfsem::LatticeTransfer lt;
 };
 
 struct mfsem_mg {

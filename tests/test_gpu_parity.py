@@ -261,12 +261,16 @@ CHAINS = {
 }
 
 
+@pytest.mark.parametrize("structured", [True, False], ids=["lattice", "elements"])
 @pytest.mark.parametrize("name", list(CHAINS))
-def test_transfers(name):
-    announce(f"transfers {name}")
+def test_transfers(name, structured):
+    """Prolongation and restriction against the oracle's matrices, both as 1D
+    lattice passes (structured levels) and per element (general meshes)."""
+    announce(f"transfers {name} structured={structured}")
     spec, chain = CHAINS[name]
     probs, mats, Ps = _levels_oracle(spec, chain)
-    ops, mg = mf.hierarchy(spec, coarsening=chain, lambda_max=[1.0] * len(mats))
+    ops, mg = mf.hierarchy(spec, coarsening=chain, lambda_max=[1.0] * len(mats),
+                           structured=structured)
     for l, P in enumerate(Ps):
         xc = synth.uniform(200 + l, P.shape[1])
         rf = synth.uniform(300 + l, P.shape[0])
@@ -277,15 +281,36 @@ def test_transfers(name):
         assert rel_l2(to_np(op.apply(to_dev(x))), mats[l] @ x) <= TOL64
 
 
+@pytest.mark.parametrize("structured", [True, False], ids=["lattice", "elements"])
+def test_transfers_f32_batched(structured):
+    """FP32 transfers of a batch of two (per-member sigma) against the oracle."""
+    announce(f"transfers f32 batch 2 structured={structured}")
+    spec, chain = CHAINS["p4-2-1"]
+    probs, mats, Ps = _levels_oracle(spec, chain)
+    sig = synth.element_sigma(210, 2, spec.n_elem)
+    ops, mg = mf.hierarchy(spec, coarsening=chain, lambda_max=[1.0] * 2 * len(mats),
+                           sigma=to_dev(sig), precision=torch.float32, structured=structured)
+    for l, P in enumerate(Ps):
+        xc = synth.uniform(220 + l, (2, P.shape[1]))
+        rf = synth.uniform(230 + l, (2, P.shape[0]))
+        yp = to_np(mg.prolong(l, to_dev(xc, torch.float32)))
+        yr = to_np(mg.restrict(l, to_dev(rf, torch.float32)))
+        for b in range(2):
+            assert rel_l2(yp[b], P @ xc[b]) <= TOL32
+            assert rel_l2(yr[b], P.T @ rf[b]) <= TOL32
+
+
+@pytest.mark.parametrize("structured", [True, False], ids=["lattice", "elements"])
 @pytest.mark.parametrize("name", list(CHAINS))
-def test_vcycle_matches_oracle(name):
-    announce(f"vcycle {name}")
+def test_vcycle_matches_oracle(name, structured):
+    announce(f"vcycle {name} structured={structured}")
     spec, chain = CHAINS[name]
     probs, mats, Ps = _levels_oracle(spec, chain)
     lam = [1.05 * osol.lanczos_lambda_max(A, 1 / A.diagonal(), synth.uniform(7, A.shape[0]))
            for A in mats]
     levels = [(A, 1 / A.diagonal(), l) for A, l in zip(mats, lam)]
-    ops, mg = mf.hierarchy(spec, coarsening=chain, lambda_max=lam, degree=3, coarse_degree=6)
+    ops, mg = mf.hierarchy(spec, coarsening=chain, lambda_max=lam, degree=3, coarse_degree=6,
+                           structured=structured)
     b = synth.uniform(500, spec.n_dof)
     z_ref = osol.vcycle(levels, Ps, b, 3, 6)
     z = to_np(mg.vcycle(to_dev(b)))
