@@ -20,6 +20,10 @@ Other workloads (--workload):
   c3 / c3-gauss         128 x 48 x 24 hexes at p = 7, SEM-NI / SEM (q = 9),
   c2-p{1..8}            the c2 slab at another degree (the matrix-based comparison
                         per degree),
+  paper-slab-p{1..4}[-gauss]
+                        the paper's 76 x 24 x 12 slab mesh (its tabulated DOF
+                        counts) with orthotropic diffusivities and Chebyshev
+                        degree 5, as in its solver set-up,
   c4                    32^3 box at p = 4 with a batch of 8 per-element
                         conductivity sets: the step's solve is a forward
                         GMG-PCG plus the adjoint gradient dL/dsigma,
@@ -106,8 +110,34 @@ def coarsening_for(p):
     return tuple(chain)
 
 
+def mg_plan(name, spec):
+    """(coarsening chain, Chebyshev degree) of a workload's multigrid.  The
+    paper-shaped slab follows the paper's set-up (degree 5) and, after the
+    p-levels, coarsens the 76 x 24 x 12 mesh twice by octree (-> 19 x 6 x 3)."""
+    if name.startswith("paper-slab"):
+        return coarsening_for(spec.p) + (("h",), ("h",)), 5
+    return coarsening_for(spec.p), 3
+
+
+def chain_str(p, chain):
+    out, cur = [f"p{p}"], p
+    for c in chain:
+        out.append(f"p{c[1]}" if c[0] == "p" else f"h(p{cur})")
+        cur = c[1] if c[0] == "p" else cur
+    return " -> ".join(out)
+
+
 def workload(name):
     import synth
+    if name.startswith("paper-slab-p"):
+        parts = name.split("-")
+        p = int(parts[2][1:])
+        gauss = len(parts) > 3 and parts[3] == "gauss"
+        spec = synth.paper_slab(p, quad="gauss" if gauss else "gll")
+        return spec, (f"the paper's slab mesh: 20x7x3 mm, 76x24x12 hexes, p={p}, "
+                      f"{'SEM (Gauss q=p+1)' if gauss else 'SEM-NI (GLL)'}, orthotropic "
+                      f"diffusivities {synth.PAPER_SLAB_SIGMA} mm^2/ms with fiber e_x and "
+                      f"sheet e_y, alpha = 3/(2*0.1 ms)")
     if name == "c2":
         return synth.C2, "c2: sheared slab 20x7x3 mm, 40x14x6 hexes, p=4, SEM-NI (GLL), rotating fibers"
     if name.startswith("c2-p"):
@@ -249,13 +279,14 @@ def main():
     log(f"workload {args.workload}: {desc}; N = {spec.n_dof:,} DOFs, {spec.n_elem:,} elements")
     dev = "cuda"
     t0 = time.perf_counter()
-    coarsening = coarsening_for(spec.p)
+    coarsening, cheb_degree = mg_plan(args.workload, spec)
     B = 1
     extra = None
     if kind == "pcg":
-        ops, mg32 = mf.hierarchy(spec, coarsening=coarsening, degree=3, precision=torch.float32)
+        ops, mg32 = mf.hierarchy(spec, coarsening=coarsening, degree=cheb_degree,
+                                 precision=torch.float32)
         op = ops[0]
-        mg64 = mf.Multigrid(ops, mg32.transfers, degree=3, precision=torch.float64)
+        mg64 = mf.Multigrid(ops, mg32.transfers, degree=cheb_degree, precision=torch.float64)
         f = torch.as_tensor(synth.uniform(2, spec.n_dof), device=dev)
     elif kind == "grad":
         from paper_2205_05136_amd import autograd as ag
@@ -371,9 +402,9 @@ def main():
         "config": {"workload": desc, "n_dof": N, "batch": B, "n_elem": spec.n_elem, "p": spec.p,
                    "quadrature": spec.quad, "nq1d": spec.q, "alpha": spec.alpha,
                    "sigma_mS_per_mm": list(spec.sigma),
-                   "multigrid": "p " + "->".join([str(spec.p)] + [str(c[1]) for c in coarsening])
-                                + ", Chebyshev degree 3 on [0.08, 1.2]*lambda_max (10 CG steps),"
-                                + " coarsest level Chebyshev degree 6",
+                   "multigrid": chain_str(spec.p, coarsening)
+                                + f", Chebyshev degree {cheb_degree} on [0.08, 1.2]*lambda_max"
+                                + f" (10 CG steps), coarsest level Chebyshev degree {2 * cheb_degree}",
                    "parallelism": "single GPU"},
         "apply": {"reps_per_step": R, "fp64_ms": round(t_apply, 5), "fp64_kernel_ms": round(t_kernel, 5),
                   "fp64_kernel_gdofs": round(NB / (t_kernel * 1e-3) / 1e9, 3),
@@ -398,8 +429,11 @@ def main():
         rel_res32 = float(torch.linalg.norm(r32) / torch.linalg.norm(f))
         rel_mixed = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
         lam64 = mg64.lambdas()[:, 0].tolist()
+        it64, it32 = rec["its"][0]
         out["pcg"] = {"fp64_ms": round(t64, 4), "mixed_ms": round(t32, 4),
-                      "fp64_iters": rec["its"][0][0], "mixed_iters": rec["its"][0][1],
+                      "fp64_iters": it64, "mixed_iters": it32,
+                      "fp64_ms_per_iteration": round(t64 / max(it64, 1), 4),
+                      "mixed_ms_per_iteration": round(t32 / max(it32, 1), 4),
                       "fp64_true_rel_residual": rel_res, "mixed_true_rel_residual": rel_res32,
                       "mixed_vs_fp64_rel_l2": rel_mixed,
                       "lambda_max_per_level": [round(v, 5) for v in lam64],

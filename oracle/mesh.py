@@ -25,6 +25,7 @@ class Mesh:
     xyz: np.ndarray        # [n_dof, 3]
     elem_dof: np.ndarray   # [n_elem, P^3] int64
     fiber: np.ndarray | None  # [n_dof, 3] or None
+    sheet: np.ndarray | None = None  # [n_dof, 3] or None
 
     @property
     def n_dof(self):
@@ -69,16 +70,19 @@ def box(spec) -> Mesh:
     gz = lattice_1d(p, nz, spec.origin[2], spec.length[2])
     Z, Y, X = np.meshgrid(gz, gy, gx, indexing="ij")
     xyz = np.stack([X.reshape(-1), Y.reshape(-1), Z.reshape(-1)], axis=1)
-    fiber = None
+    fiber = sheet = None
     if spec.fiber:
         t = (xyz[:, 2] - spec.origin[2]) / spec.length[2]
         theta = spec.theta0 + (spec.theta1 - spec.theta0) * t
         fiber = np.stack([np.cos(theta), np.sin(theta), np.zeros_like(theta)], axis=1)
+        if spec.sheet:
+            sheet = np.stack([-np.sin(theta), np.cos(theta), np.zeros_like(theta)], axis=1)
     if spec.shear_amp != 0.0:
         hx = spec.length[0] / nx
         d = spec.shear_amp * hx * np.sin(2 * np.pi * (xyz[:, 0] - spec.origin[0]) / spec.length[0])
         xyz = xyz + d[:, None]
-    return Mesh(p=p, n=(nx, ny, nz), xyz=xyz, elem_dof=elem_dof_map(p, (nx, ny, nz)), fiber=fiber)
+    return Mesh(p=p, n=(nx, ny, nz), xyz=xyz, elem_dof=elem_dof_map(p, (nx, ny, nz)), fiber=fiber,
+                sheet=sheet)
 
 
 def element_ids(n: tuple):
@@ -104,16 +108,18 @@ def element_nodes(spec, elems):
     y = spec.origin[1] + hy * (ey[:, None] + 0.5 * (xi[B][None, :] + 1.0))
     z = spec.origin[2] + hz * (ez[:, None] + 0.5 * (xi[C][None, :] + 1.0))
     xyz = np.stack([x, y, z], axis=-1)
-    fib = None
+    fib = she = None
     if spec.fiber:
         theta = spec.theta0 + (spec.theta1 - spec.theta0) * (z - spec.origin[2]) / spec.length[2]
         fib = np.stack([np.cos(theta), np.sin(theta), np.zeros_like(theta)], axis=-1)
+        if spec.sheet:
+            she = np.stack([-np.sin(theta), np.cos(theta), np.zeros_like(theta)], axis=-1)
     if spec.shear_amp != 0.0:
         d = spec.shear_amp * hx * np.sin(2 * np.pi * (x - spec.origin[0]) / spec.length[0])
         xyz = xyz + d[..., None]
     NX, NY = p * nx + 1, p * ny + 1
     gidx = (p * ex[:, None] + A) + NX * ((p * ey[:, None] + B) + NY * (p * ez[:, None] + C))
-    return xyz, fib, gidx
+    return xyz, fib, she, gidx
 
 
 def elements_of_dof(spec, g):

@@ -163,8 +163,10 @@ class Problem:
     # -- element level ----------------------------------------------------------
     def elem_geometry(self, elems):
         X = self.mesh.xyz[self.mesh.elem_dof[elems]]
-        f = None if self.mesh.fiber is None else self.mesh.fiber[self.mesh.elem_dof[elems]]
-        return geometry(X, f, None, self.map_p, self.pts, self.w)
+        ed = self.mesh.elem_dof[elems]
+        f = None if self.mesh.fiber is None else self.mesh.fiber[ed]
+        s = None if self.mesh.sheet is None else self.mesh.sheet[ed]
+        return geometry(X, f, s, self.map_p, self.pts, self.w)
 
     def elem_matrices(self, elems, parts=False):
         geo = self.elem_geometry(elems)
@@ -227,8 +229,8 @@ def apply_rows(spec, x_fn, rows, sigma=None):
     out = np.zeros(len(rows))
     for r, g in enumerate(rows):
         elems = mesh_mod.elements_of_dof(spec, int(g))
-        xyz, fib, gidx = mesh_mod.element_nodes(spec, elems)
-        geo = geometry(xyz, fib, None, spec.p, pts, w)
+        xyz, fib, she, gidx = mesh_mod.element_nodes(spec, elems)
+        geo = geometry(xyz, fib, she, spec.p, pts, w)
         sig = (np.broadcast_to(np.asarray(spec.sigma, float), (len(elems), 3))
                if sigma is None else sigma[elems])
         M, K = element_matrices(geo, sig, spec.p, pts, spec.alpha)

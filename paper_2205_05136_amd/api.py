@@ -138,7 +138,7 @@ class Operator:
     def from_spec(cls, spec, box=None, device="cuda", **kw):
         box = box or Box.from_spec(spec, device=device)
         args = dict(quad=spec.quad, nq1d=spec.q if spec.quad == "gauss" else 0,
-                    sigma_const=spec.sigma, alpha=spec.alpha)
+                    sigma_const=spec.sigma, alpha=spec.alpha, sheet=spec_sheet(spec, box))
         args.update(kw)
         return cls(box, **args)
 
@@ -323,6 +323,15 @@ class Multigrid:
         return torch.tensor(list(arr), dtype=torch.float64).reshape(len(self.ops), self.batch)
 
 
+def spec_sheet(spec, box):
+    """The sheet field of a spec with a sheet (the in-plane normal of the box's
+    fiber, (-a_y, a_x, 0)), or None."""
+    if not getattr(spec, "sheet", False):
+        return None
+    f = box.fiber
+    return torch.stack([-f[:, 1], f[:, 0], torch.zeros_like(f[:, 0])], dim=1).contiguous()
+
+
 def hierarchy(spec, fine_box: Box | None = None, coarsening=(("p", 2), ("p", 1)),
               precision=torch.float64, device="cuda", sigma=None, xyz=None, structured=True,
               **mg_kw):
@@ -330,13 +339,16 @@ def hierarchy(spec, fine_box: Box | None = None, coarsening=(("p", 2), ("p", 1))
 
     coarsening: sequence of ("p", degree) and ("h",) steps from the finest level.
     p-levels keep the geometry map of the level they coarsen; h-levels build the
-    octree-coarser box from the same recipe.  structured=False builds every
-    level as a general mesh (element kernels and element transfers)."""
+    octree-coarser box from the same recipe.  Levels below the finest use GLL
+    quadrature (SEM-NI) whatever the finest level's rule: the preconditioner
+    only needs a spectrally equivalent operator, and the collocated one is the
+    cheapest.  structured=False builds every level as a general mesh (element
+    kernels and element transfers)."""
     fine_box = fine_box or Box.from_spec(spec, device=device)
     store = dict(store_f64=True, store_f32=(precision == torch.float32))
     kw = dict(sigma_const=spec.sigma, alpha=spec.alpha, sigma=sigma, structured=structured)
     ops = [Operator(fine_box, quad=spec.quad, nq1d=spec.q if spec.quad == "gauss" else 0,
-                    xyz=xyz, **store, **kw)]
+                    xyz=xyz, sheet=spec_sheet(spec, fine_box), **store, **kw)]
     boxes = [fine_box]
     geo_box, geo_xyz, n = fine_box, xyz, spec.n
     amp = spec.shear_amp
@@ -347,7 +359,8 @@ def hierarchy(spec, fine_box: Box | None = None, coarsening=(("p", 2), ("p", 1))
             pc = step[1]
             dofs = Box(pc, n, spec.origin, spec.length, amp, spec.fiber, spec.theta0,
                        spec.theta1, device)
-            ops.append(Operator(dofs, geometry=geo_box, xyz=geo_xyz, **store, **kw))
+            ops.append(Operator(dofs, geometry=geo_box, xyz=geo_xyz,
+                                sheet=spec_sheet(spec, geo_box), **store, **kw))
             transfers.append(("p",))
         else:
             if sigma is not None:
@@ -360,7 +373,7 @@ def hierarchy(spec, fine_box: Box | None = None, coarsening=(("p", 2), ("p", 1))
             geo_box = Box(prev.p, nc, spec.origin, spec.length, amp, spec.fiber, spec.theta0,
                           spec.theta1, device)
             geo_xyz = None
-            ops.append(Operator(geo_box, **store, **kw))
+            ops.append(Operator(geo_box, sheet=spec_sheet(spec, geo_box), **store, **kw))
             transfers.append(("h", parent, child))
             n = nc
             dofs = geo_box

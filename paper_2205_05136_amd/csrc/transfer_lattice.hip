@@ -171,14 +171,11 @@ void lattice_transfer_layout(LatticeTransfer& t, const mfsem_op& fine, const mfs
     t.bidx[d] = a.take_n<int32_t>(h.bidx.size());
     t.bcoef[d] = a.take(h.bcoef.size() * word);
   }
-  const int64_t nfx = t.host[0].nf, nfy = t.host[1].nf, nfz = t.host[2].nf;
-  const int64_t ncx = t.host[0].nc, ncy = t.host[1].nc, ncz = t.host[2].nc;
-  // prolongation: (nfx, ncy, ncz) then (nfx, nfy, ncz); restriction:
-  // (ncx, nfy, nfz) then (ncx, ncy, nfz)
-  const int64_t s1 = std::max(nfx * ncy * ncz, ncx * nfy * nfz);
-  const int64_t s2 = std::max(nfx * nfy * ncz, ncx * ncy * nfz);
-  t.s1 = a.take((size_t)s1 * batch * word);
-  t.s2 = a.take((size_t)s2 * batch * word);
+  const int64_t nfx = t.host[0].nf, nfy = t.host[1].nf;
+  const int64_t ncy = t.host[1].nc, ncz = t.host[2].nc;
+  // both directions pass through (nfx, ncy, ncz) in s1 and (nfx, nfy, ncz) in s2
+  t.s1 = a.take((size_t)(nfx * ncy * ncz) * batch * word);
+  t.s2 = a.take((size_t)(nfx * nfy * ncz) * batch * word);
   t.word = word;
 }
 
@@ -234,8 +231,9 @@ void lattice_prolong(const LatticeTransfer& t, int batch, const T* xc, T* xf, bo
   }
 }
 
-// transposed passes: (nfx, nfy, nfz) -> (ncx, nfy, nfz) -> (ncx, ncy, nfz)
-// -> (ncx, ncy, ncz)
+// transposed passes, z first so that the pass over the full fine lattice
+// reads its coefficient rows at a block-uniform coarse z:
+// (nfx, nfy, nfz) -> (nfx, nfy, ncz) -> (nfx, ncy, ncz) -> (ncx, ncy, ncz)
 template <typename T>
 void lattice_restrict(const LatticeTransfer& t, int batch, const T* bf, const T* tf, T* rc,
                       hipStream_t s) {
@@ -243,22 +241,22 @@ void lattice_restrict(const LatticeTransfer& t, int batch, const T* bf, const T*
   T* s1 = static_cast<T*>(t.s1);
   T* s2 = static_cast<T*>(t.s2);
   {
-    const int id[3] = {hx.nf, hy.nf, hz.nf}, od[3] = {hx.nc, hy.nf, hz.nf};
+    const int id[3] = {hx.nf, hy.nf, hz.nf}, od[3] = {hx.nf, hy.nf, hz.nc};
     if (tf)
-      pass<T, 0, true, true, false>(bf, tf, s1, nullptr, od, id, t.bidx[0], t.bcoef[0], hx.Wb,
+      pass<T, 2, true, true, false>(bf, tf, s2, nullptr, od, id, t.bidx[2], t.bcoef[2], hz.Wb,
                                     batch, s);
     else
-      pass<T, 0, true, false, false>(bf, nullptr, s1, nullptr, od, id, t.bidx[0], t.bcoef[0],
-                                     hx.Wb, batch, s);
+      pass<T, 2, true, false, false>(bf, nullptr, s2, nullptr, od, id, t.bidx[2], t.bcoef[2],
+                                     hz.Wb, batch, s);
   }
   {
-    const int id[3] = {hx.nc, hy.nf, hz.nf}, od[3] = {hx.nc, hy.nc, hz.nf};
-    pass<T, 1, true, false, false>(s1, nullptr, s2, nullptr, od, id, t.bidx[1], t.bcoef[1], hy.Wb,
+    const int id[3] = {hx.nf, hy.nf, hz.nc}, od[3] = {hx.nf, hy.nc, hz.nc};
+    pass<T, 1, true, false, false>(s2, nullptr, s1, nullptr, od, id, t.bidx[1], t.bcoef[1], hy.Wb,
                                    batch, s);
   }
   {
-    const int id[3] = {hx.nc, hy.nc, hz.nf}, od[3] = {hx.nc, hy.nc, hz.nc};
-    pass<T, 2, true, false, false>(s2, nullptr, rc, nullptr, od, id, t.bidx[2], t.bcoef[2], hz.Wb,
+    const int id[3] = {hx.nf, hy.nc, hz.nc}, od[3] = {hx.nc, hy.nc, hz.nc};
+    pass<T, 0, true, false, false>(s1, nullptr, rc, nullptr, od, id, t.bidx[0], t.bcoef[0], hx.Wb,
                                    batch, s);
   }
 }

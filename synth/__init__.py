@@ -32,10 +32,13 @@ class BoxSpec:
         d = shear_amp * hx * sin(2*pi*(x - x0)/Lx), x the undeformed first
         coordinate and hx the element edge along x;
       * optional fiber a = (cos t, sin t, 0), t rising linearly from theta0 at
-        z = z0 to theta1 at z = z0 + Lz (undeformed z), stored at every node.
+        z = z0 to theta1 at z = z0 + Lz (undeformed z), stored at every node;
+      * optional sheet (with the fiber) s = (-sin t, cos t, 0) at every node, so
+        that the cross-fiber direction is e_z.
     Physics: conductivity sigma = (sigma_l, sigma_t, sigma_n); with a fiber and
-    no sheet the tensor is sigma_t*I + (sigma_l - sigma_t)*a a^T; without a fiber
-    it is sigma_t*I.  `alpha` multiplies the mass matrix.
+    a sheet the tensor is sigma_l a a^T + sigma_t s s^T + sigma_n n n^T; with a
+    fiber and no sheet it is sigma_t*I + (sigma_l - sigma_t)*a a^T; without a
+    fiber it is sigma_t*I.  `alpha` multiplies the mass matrix.
     """
 
     p: int
@@ -50,6 +53,7 @@ class BoxSpec:
     alpha: float = 1.0
     quad: str = GLL
     nq1d: int = 0  # 0 -> p+1
+    sheet: bool = False
 
     @property
     def q(self) -> int:
@@ -93,6 +97,23 @@ C4 = BoxSpec(p=4, n=(32, 32, 32), length=(16.0, 16.0, 16.0), fiber=True,
              theta0=-60 * DEG, theta1=60 * DEG, sigma=SLAB_SIGMA, alpha=SLAB_ALPHA)
 C5 = BoxSpec(p=5, n=(128, 128, 64), length=(20.0, 20.0, 10.0), fiber=True,
              theta0=-60 * DEG, theta1=60 * DEG, sigma=SLAB_SIGMA, alpha=SLAB_ALPHA)
+
+# The paper's slab mesh (Section 5.1: 76 x 24 x 12 hexahedra on the 20 x 7 x 3 mm
+# slab, whose Q1..Q4 node counts are the DOF counts the paper tabulates), with
+# the paper's orthotropic conductivities read as diffusivities (chi = Cm = 1)
+# and alpha = 3 / (2 dt) for BDF2 at dt = 0.1 ms.  Fiber e_x, sheet e_y: the
+# paper's fiber field is not available, so this stands in for the shapes only.
+PAPER_SLAB_N = (76, 24, 12)
+PAPER_SLAB_SIGMA = (0.07643, 0.03494, 0.01125)
+PAPER_SLAB_ALPHA = 3.0 / (2.0 * 0.1)
+
+
+def paper_slab(p: int, quad: str = GLL) -> BoxSpec:
+    """The paper's slab mesh at degree p; SEM uses Legendre-Gauss with p+1 points."""
+    return BoxSpec(p=p, n=PAPER_SLAB_N, length=SLAB_LEN, fiber=True, theta0=0.0, theta1=0.0,
+                   sheet=True, sigma=PAPER_SLAB_SIGMA, alpha=PAPER_SLAB_ALPHA, quad=quad,
+                   nq1d=p + 1 if quad == GAUSS else 0)
+
 
 # The p-sweep: the same sheared slab at about 51M DOFs for every p
 # (a 896 x 336 x 168 node lattice, rounded to whole elements).

@@ -233,21 +233,43 @@ def test_apply_sheet_orthotropic():
     assert rel_l2(to_np(op.apply(to_dev(x))), y_ref) <= TOL64
 
 
+@pytest.mark.parametrize("quad", ["gll", "gauss"])
+def test_paper_slab_shape_sheet_hierarchy(quad):
+    """The paper-shaped workload's set-up at a small size: orthotropic tensor from
+    the spec's sheet, p- then h-coarsening, Chebyshev degree 5; apply, V-cycle and
+    PCG against the oracle."""
+    announce(f"paper-slab shape {quad}")
+    spec = synth.paper_slab(2, quad=quad).with_(n=(8, 4, 4))
+    chain = (("p", 1), ("h",))
+    probs, mats, Ps = _levels_oracle(spec, chain)
+    ops, mg = mf.hierarchy(spec, coarsening=chain, degree=5)
+    for l, op in enumerate(ops):
+        x = synth.uniform(410 + l, op.n_dof)
+        assert rel_l2(to_np(op.apply(to_dev(x))), mats[l] @ x) <= TOL64
+    lam = mg.lambdas().numpy()[:, 0]
+    levels = [(A, 1 / A.diagonal(), float(l)) for A, l in zip(mats, lam)]
+    b = synth.uniform(510, spec.n_dof)
+    assert rel_l2(to_np(mg.vcycle(to_dev(b))), osol.vcycle(levels, Ps, b, 5, 10)) <= TOL64
+    u, info = mf.pcg(ops[0], to_dev(b), mg=mg, rtol=1e-12, max_it=100)
+    assert np.linalg.norm(b - mats[0] @ to_np(u)) <= 1.01e-12 * np.linalg.norm(b)
+
+
 # -------------------------------------------------------------- multigrid ---
 def _levels_oracle(spec, chain):
-    """Oracle level matrices and prolongations for a coarsening chain."""
+    """Oracle level matrices and prolongations for a coarsening chain (levels
+    below the finest use GLL quadrature, SEM-NI, as the library's hierarchy)."""
     probs = [oop.Problem(spec)]
     Ps = []
     cur, n, p = spec, spec.n, spec.p
     for step in chain:
         if step[0] == "p":
-            probs.append(oop.Problem(cur, dof_p=step[1]))
+            probs.append(oop.Problem(cur, dof_p=step[1], quad="gll"))
             Ps.append(omg.prolongation_p(n, p, step[1]))
             p = step[1]
         else:
             nc = tuple(k // 2 for k in n)
             Ps.append(omg.prolongation_h(n, p))
-            cur = cur.with_(n=nc, shear_amp=cur.shear_amp / 2, p=p)
+            cur = cur.with_(n=nc, shear_amp=cur.shear_amp / 2, p=p, quad="gll", nq1d=0)
             probs.append(oop.Problem(cur))
             n = nc
     mats = [pr.assemble()[0] for pr in probs]

@@ -46,6 +46,18 @@ MUTATIONS = {
                               (lambda orig: lambda sig, f=None, s=None:
                                orig(sig[..., [1, 0, 2]], f, s))(operator.sigma_tensor)),
         [lambda: pins.test_anisotropic_energy_of_linear_functions("gll", 0)]),
+    # sigma_t and sigma_n exchanged (sheet and cross-fiber directions mixed up)
+    "sigma_t and sigma_n swapped": (
+        lambda mp: mp.setattr(operator, "sigma_tensor",
+                              (lambda orig: lambda sig, f=None, s=None:
+                               orig(sig[..., [0, 2, 1]], f, s))(operator.sigma_tensor)),
+        [lambda: pins.test_orthotropic_energy_along_principal_directions("gll", 0)]),
+    # sheet not used (transversely isotropic tensor although a sheet is given)
+    "sheet dropped": (
+        lambda mp: mp.setattr(operator, "sigma_tensor",
+                              (lambda orig: lambda sig, f=None, s=None: orig(sig, f, None))(
+                                  operator.sigma_tensor)),
+        [lambda: pins.test_orthotropic_energy_along_principal_directions("gauss", 4)]),
     # fiber direction not used (isotropic sigma_t I regardless of the fiber)
     "fiber term dropped": (
         lambda mp: mp.setattr(operator, "sigma_tensor",

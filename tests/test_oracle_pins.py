@@ -209,6 +209,40 @@ def test_anisotropic_energy_of_linear_functions(quad, q):
         assert abs(u @ (K @ u) - ref) < 1e-10 * ref
 
 
+@pytest.mark.parametrize("quad,q", [("gll", 0), ("gauss", 4)])
+def test_orthotropic_energy_along_principal_directions(quad, q):
+    """With a uniform fiber a and sheet s (Section 2: the tensor has the
+    eigenpairs (sigma_l, a), (sigma_t, s), (sigma_n, a x s)), u = c.x has
+    u^T K u = |Omega| sum_i sigma_i (c . e_i)^2 over that frame: pins the sheet
+    and cross-fiber terms (a swap of sigma_t and sigma_n, or a sheet left
+    unnormalised, fails)."""
+    th = 0.4
+    sl, st, sn = 0.17, 0.05, 0.011
+    spec = _slab_small(3, quad, q).with_(theta0=th, theta1=th, sheet=True, sigma=(sl, st, sn))
+    prob = operator.Problem(spec)
+    assert prob.mesh.sheet is not None
+    _, _, K = prob.assemble()
+    a = np.array([math.cos(th), math.sin(th), 0.0])
+    s_ = np.array([-math.sin(th), math.cos(th), 0.0])
+    n_ = np.array([0.0, 0.0, 1.0])
+    for c, ref in ((a, sl), (s_, st), (n_, sn),
+                   (0.3 * a - 1.2 * s_ + 0.7 * n_, 0.09 * sl + 1.44 * st + 0.49 * sn)):
+        u = prob.mesh.xyz @ c
+        assert abs(u @ (K @ u) - ref * 420.0) < 1e-10 * ref * 420.0
+
+
+def test_paper_slab_workload_sizes():
+    """The paper-shaped slab workload has the DOF counts the paper tabulates,
+    and its orthotropic frame is (e_x, e_y, e_z)."""
+    gold = json.load(open(os.path.join(GOLD, "paper_slab_dofs.json")))
+    for p in (1, 2, 3, 4):
+        spec = synth.paper_slab(p)
+        assert spec.n_dof == gold["dofs"][str(p)]
+    m = mesh.box(synth.paper_slab(1).with_(n=(4, 2, 2)))
+    np.testing.assert_array_equal(m.fiber, np.tile([1.0, 0.0, 0.0], (m.n_dof, 1)))
+    np.testing.assert_array_equal(m.sheet, np.tile([0.0, 1.0, 0.0], (m.n_dof, 1)))
+
+
 def _rotation(a, b, c):
     Rz = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
     Ry = np.array([[math.cos(b), 0, math.sin(b)], [0, 1, 0], [-math.sin(b), 0, math.cos(b)]])
