@@ -101,13 +101,20 @@ def measured_traffic(kernel, source, workload):
     return int(entry["read_bytes"] + entry["write_bytes"])
 
 
+# p-multigrid degree sequences, measured on the 51M-DOF slab (PCG to 1e-10, FP64 and
+# mixed, Chebyshev degree 3): halving the degree from p = 3, 5, 6, 7 costs 15-18
+# iterations where these sequences need 9-12, and 20-23% of the solve time at p = 3, 5
+QSEQ = {1: (), 2: (1,), 3: (2, 1), 4: (2, 1), 5: (3, 1), 6: (4, 2, 1), 7: (5, 3, 1)}
+
+
 def coarsening_for(p):
-    """p-coarsening by halving the degree down to 1 (4 -> 2 -> 1, 7 -> 3 -> 1)."""
-    chain, q = [], p
-    while q > 1:
-        q = max(1, q // 2)
-        chain.append(("p", q))
-    return tuple(chain)
+    """p-coarsening chain from degree p down to 1 (above 7: steps of 2 until 7)."""
+    seq = []
+    while p > 7:
+        p -= 2
+        seq.append(p)
+    seq += QSEQ[p]
+    return tuple(("p", q) for q in seq)
 
 
 def mg_plan(name, spec):
@@ -117,6 +124,15 @@ def mg_plan(name, spec):
     if name.startswith("paper-slab"):
         return coarsening_for(spec.p) + (("h",), ("h",)), 5
     return coarsening_for(spec.p), 3
+
+
+def parse_chain(text):
+    """'p5,p3,p1,h' -> (("p", 5), ("p", 3), ("p", 1), ("h",))."""
+    out = []
+    for tok in text.split(","):
+        tok = tok.strip()
+        out.append(("h",) if tok == "h" else ("p", int(tok[1:])))
+    return tuple(out)
 
 
 def chain_str(p, chain):
@@ -256,6 +272,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--coarsening", default=None,
+                    help="multigrid chain below the finest level, e.g. p5,p3,p1 or p2,p1,h "
+                         "(default: the workload's)")
+    ap.add_argument("--cheb-degree", type=int, default=None,
+                    help="Chebyshev degree of the smoother (default: the workload's)")
     ap.add_argument("--no-matrix-based", action="store_true",
                     help="skip the assembled-matrix (CSR) comparison")
     ap.add_argument("--copy-ref", action="store_true",
@@ -280,6 +301,10 @@ def main():
     dev = "cuda"
     t0 = time.perf_counter()
     coarsening, cheb_degree = mg_plan(args.workload, spec)
+    if args.coarsening:
+        coarsening = parse_chain(args.coarsening)
+    if args.cheb_degree:
+        cheb_degree = args.cheb_degree
     B = 1
     extra = None
     if kind == "pcg":
@@ -294,7 +319,7 @@ def main():
         sig = torch.as_tensor(synth.element_sigma(4, B, spec.n_elem), device=dev)
         fB = torch.as_tensor(synth.uniform(5, (B, spec.n_dof)), device=dev)
         ut = torch.as_tensor(synth.uniform(6, (B, spec.n_dof)), device=dev)
-        solver = ag.Solver(spec, batch=B, coarsening=coarsening, rtol=1e-10,
+        solver = ag.Solver(spec, batch=B, coarsening=coarsening, degree=cheb_degree, rtol=1e-10,
                            precision=torch.float64)
         solver.set_sigma(sig)
         op = solver.ops[0]
@@ -303,7 +328,7 @@ def main():
         from paper_2205_05136_amd.monodomain import Monodomain, Stimulus
         sim = Monodomain(spec, dt=0.05, chi=synth.CHI, cm=synth.CM, ap_params=synth.AP_PARAMS,
                          stimulus=Stimulus((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 50.0, 2.0),
-                         coarsening=coarsening, degree=3, precision=torch.float32)
+                         coarsening=coarsening, degree=cheb_degree, precision=torch.float32)
         op = sim.op
     else:
         op = mf.Operator.from_spec(spec, store_f32=True)
