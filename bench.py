@@ -29,7 +29,9 @@ Other workloads (--workload):
                         GMG-PCG plus the adjoint gradient dL/dsigma,
   c5                    128 x 128 x 64 box at p = 5: the step's solve is one
                         IMEX monodomain time step (run --steps 100 for the
-                        full 5 ms).
+                        full 5 ms),
+  c5-bdf2               the same with the paper's BDF2 partitioned scheme and
+                        activation times.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
@@ -103,13 +105,23 @@ def measured_traffic(kernel, source, workload):
 
 # p-multigrid degree sequences, measured on the 51M-DOF slab (PCG to 1e-10, FP64 and
 # mixed, Chebyshev degree 3): halving the degree from p = 3, 5, 6, 7 costs 15-18
-# iterations where these sequences need 9-12, and 20-23% of the solve time at p = 3, 5
+# iterations where these sequences need 9-12, and 20-23% of the solve time at p = 3, 5.
+# On meshes of a few hundred thousand DOFs the solve is bound by launch latency and
+# the extra levels cost more than the iterations they save (c2 slab at p = 3..7:
+# 1.4-5.7 ms with halving against 2.0-7.0 ms), so small problems halve the degree.
 QSEQ = {1: (), 2: (1,), 3: (2, 1), 4: (2, 1), 5: (3, 1), 6: (4, 2, 1), 7: (5, 3, 1)}
+SMALL_DOFS = 4_000_000
 
 
-def coarsening_for(p):
-    """p-coarsening chain from degree p down to 1 (above 7: steps of 2 until 7)."""
+def coarsening_for(p, n_dof=None):
+    """p-coarsening chain from degree p down to 1: the measured sequences (above 7:
+    steps of 2 until 7), or halving the degree for meshes under SMALL_DOFS."""
     seq = []
+    if n_dof is not None and n_dof < SMALL_DOFS:
+        while p > 1:
+            p = max(1, p // 2)
+            seq.append(p)
+        return tuple(("p", q) for q in seq)
     while p > 7:
         p -= 2
         seq.append(p)
@@ -122,8 +134,8 @@ def mg_plan(name, spec):
     paper-shaped slab follows the paper's set-up (degree 5) and, after the
     p-levels, coarsens the 76 x 24 x 12 mesh twice by octree (-> 19 x 6 x 3)."""
     if name.startswith("paper-slab"):
-        return coarsening_for(spec.p) + (("h",), ("h",)), 5
-    return coarsening_for(spec.p), 3
+        return coarsening_for(spec.p, spec.n_dof) + (("h",), ("h",)), 5
+    return coarsening_for(spec.p, spec.n_dof), 3
 
 
 def parse_chain(text):
@@ -177,6 +189,10 @@ def workload(name):
     if name == "c5":
         return synth.C5, ("c5: box 20x20x10 mm, 128x128x64 hexes, p=5, SEM-NI; IMEX monodomain "
                           "steps (Aliev-Panfilov + mixed-precision GMG-PCG)")
+    if name == "c5-bdf2":
+        return synth.C5, ("c5 with the paper's BDF2 partitioned scheme: box 20x20x10 mm, "
+                          "128x128x64 hexes, p=5, SEM-NI; implicit gating, lumped ionic "
+                          "current, activation times (Aliev-Panfilov + mixed-precision GMG-PCG)")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -294,7 +310,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     spec, desc = workload(args.workload)
-    kind = {"c4": "grad", "c5": "monodomain"}.get(args.workload, "pcg")
+    kind = {"c4": "grad", "c5": "monodomain", "c5-bdf2": "monodomain"}.get(args.workload, "pcg")
     if args.no_pcg and kind == "pcg":
         kind = None
     log(f"workload {args.workload}: {desc}; N = {spec.n_dof:,} DOFs, {spec.n_elem:,} elements")
@@ -328,7 +344,8 @@ def main():
         from paper_2205_05136_amd.monodomain import Monodomain, Stimulus
         sim = Monodomain(spec, dt=0.05, chi=synth.CHI, cm=synth.CM, ap_params=synth.AP_PARAMS,
                          stimulus=Stimulus((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 50.0, 2.0),
-                         coarsening=coarsening, degree=cheb_degree, precision=torch.float32)
+                         coarsening=coarsening, degree=cheb_degree, precision=torch.float32,
+                         scheme="bdf2" if args.workload == "c5-bdf2" else "imex1")
         op = sim.op
     else:
         op = mf.Operator.from_spec(spec, store_f32=True)
@@ -480,7 +497,13 @@ def main():
                              "solve_ms": round(sum(st.solve_ms[-k:]) / k, 4),
                              "pcg_iters_mean": round(sum(its) / k, 3),
                              "V_range_mV": [round(float(sim.V.min()), 3), round(float(sim.V.max()), 3)],
-                             "sim_time_ms": round(sim.t, 4), "setup_s": round(t_setup, 3)}
+                             "sim_time_ms": round(sim.t, 4), "setup_s": round(t_setup, 3),
+                             "scheme": sim.scheme}
+        if sim.scheme == "bdf2":
+            act = sim.act[sim.act >= 0]
+            out["monodomain"]["activated_fraction"] = round(act.numel() / sim.act.numel(), 5)
+            out["monodomain"]["activation_ms_range"] = (
+                [round(float(act.min()), 4), round(float(act.max()), 4)] if act.numel() else None)
     if kind == "pcg" and not args.no_matrix_based:
         out["matrix_based"] = matrix_based(mf, op, x, t_kernel, spec)
     if args.copy_ref:

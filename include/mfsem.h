@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MFSEM_ABI_VERSION 2
+#define MFSEM_ABI_VERSION 3
 #define MFSEM_MAX_P 8
 
 typedef enum {
@@ -227,10 +227,13 @@ mfsem_status mfsem_csr_nnz(const mfsem_op* op, int64_t* nnz);
 mfsem_status mfsem_csr_assemble(const mfsem_op* op, int64_t* row_ptr, int32_t* col, double* val,
                                 void* stream);
 
-/* y = A x with a CSR matrix (one wavefront per row); x, y [device][n_rows]
- * FP64, not aliased.                                                         */
-mfsem_status mfsem_csr_spmv(int64_t n_rows, const int64_t* row_ptr, const int32_t* col,
-                            const double* val, const double* x, double* y, void* stream);
+/* y = A x with a CSR matrix; x, y [device][n_rows] FP64, not aliased.  nnz
+ * [host] is the number of stored entries (row_ptr[n_rows], from
+ * mfsem_csr_nnz); its mean per row picks 16 or 32 lanes per row.  A wrong
+ * nnz only changes that choice, never the result.                           */
+mfsem_status mfsem_csr_spmv(int64_t n_rows, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col, const double* val, const double* x, double* y,
+                            void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Geometric multigrid V-cycle (Section 4.3).  Levels are operators created by

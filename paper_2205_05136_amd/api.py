@@ -227,7 +227,7 @@ class CsrMatrix:
         """y = A x (mfsem_csr_spmv)."""
         y = torch.empty_like(x) if out is None else out
         _pointwise(self.n, self.device, x, y)
-        L.check(L.load().mfsem_csr_spmv(self.n, _ptr(self.row_ptr), _ptr(self.col),
+        L.check(L.load().mfsem_csr_spmv(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col),
                                         _ptr(self.val), _ptr(x), _ptr(y), _stream()))
         return y
 

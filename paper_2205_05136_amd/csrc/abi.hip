@@ -381,13 +381,14 @@ mfsem_status mfsem_csr_assemble(const mfsem_op* op, int64_t* row_ptr, int32_t* c
   });
 }
 
-mfsem_status mfsem_csr_spmv(int64_t n_rows, const int64_t* row_ptr, const int32_t* col,
-                            const double* val, const double* x, double* y, void* stream) {
+mfsem_status mfsem_csr_spmv(int64_t n_rows, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col, const double* val, const double* x, double* y,
+                            void* stream) {
   return guarded([&] {
-    require(n_rows >= 0, "n_rows must be >= 0");
+    require(n_rows >= 0 && nnz >= 0, "n_rows and nnz must be >= 0");
     require(n_rows == 0 || (row_ptr && col && val && x && y), "NULL argument");
     require(x != y, "x and y must not alias");
-    csr_spmv(n_rows, row_ptr, col, val, x, y, as_stream(stream));
+    csr_spmv(n_rows, nnz, row_ptr, col, val, x, y, as_stream(stream));
   });
 }
 

@@ -140,18 +140,40 @@ __global__ __launch_bounds__(CT) void csr_values_kernel(Lattice L, int P, const 
   }
 }
 
+// LPR lanes per row (a power of two dividing 64), so that 64 / LPR rows share a
+// wave and their row-offset, column and x loads overlap; each lane keeps four
+// independent partial sums so that several loads are in flight.  Measured on
+// the c2 slab: 16 lanes are fastest up to ~200 entries per row (p <= 4), 32
+// above; one wave per row is 12-38% slower, non-temporal loads 10-60% slower.
+template <int LPR>
 __global__ __launch_bounds__(CT) void csr_spmv_kernel(int64_t n_rows, const int64_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ col,
                                                       const double* __restrict__ val,
                                                       const double* __restrict__ x,
                                                       double* __restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  for (int64_t g = ((int64_t)blockIdx.x * CT + threadIdx.x) >> 6; g < n_rows;
-       g += ((int64_t)gridDim.x * CT) >> 6) {
+  const int lane = threadIdx.x & (LPR - 1);
+  const int64_t rows_per_grid = ((int64_t)gridDim.x * CT) / LPR;
+  for (int64_t g = ((int64_t)blockIdx.x * CT + threadIdx.x) / LPR; g < n_rows; g += rows_per_grid) {
     const int64_t a = row_ptr[g], b = row_ptr[g + 1];
-    double s = 0.0;
-    for (int64_t k = a + lane; k < b; k += 64) s += val[k] * x[col[k]];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t k = a + lane;
+    for (; k + 3 * LPR < b; k += 4 * LPR) {
+      const double v0 = val[k];
+      const double v1 = val[k + LPR];
+      const double v2 = val[k + 2 * LPR];
+      const double v3 = val[k + 3 * LPR];
+      const int32_t c0 = col[k];
+      const int32_t c1 = col[k + LPR];
+      const int32_t c2 = col[k + 2 * LPR];
+      const int32_t c3 = col[k + 3 * LPR];
+      s0 += v0 * x[c0];
+      s1 += v1 * x[c1];
+      s2 += v2 * x[c2];
+      s3 += v3 * x[c3];
+    }
+    for (; k < b; k += LPR) s0 += val[k] * x[col[k]];
+    double s = (s0 + s1) + (s2 + s3);
+    for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
     if (lane == 0) y[g] = s;
   }
 }
@@ -167,8 +189,8 @@ Lattice lattice_of(const mfsem_op& op) {
   return L;
 }
 
-unsigned row_blocks(int64_t rows) {
-  int64_t b = (rows * 64 + CT - 1) / CT;
+unsigned row_blocks(int64_t rows, int lanes_per_row = 64) {
+  int64_t b = (rows * lanes_per_row + CT - 1) / CT;
   if (b > 65536) b = 65536;
   return (unsigned)(b < 1 ? 1 : b);
 }
@@ -192,10 +214,15 @@ void csr_assemble(const mfsem_op& op, int64_t* row_ptr, int32_t* col, double* va
   MFSEM_LAUNCH("csr_values_kernel");
 }
 
-void csr_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+void csr_spmv(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col, const double* val,
               const double* x, double* y, hipStream_t s) {
   if (n <= 0) return;
-  csr_spmv_kernel<<<row_blocks(n), CT, 0, s>>>(n, row_ptr, col, val, x, y);
+  const int64_t mean = nnz / n;  // lanes per row from the mean row length
+  if (mean <= 256) {
+    csr_spmv_kernel<16><<<row_blocks(n, 16), CT, 0, s>>>(n, row_ptr, col, val, x, y);
+  } else {
+    csr_spmv_kernel<32><<<row_blocks(n, 32), CT, 0, s>>>(n, row_ptr, col, val, x, y);
+  }
   MFSEM_LAUNCH("csr_spmv_kernel");
 }
 

@@ -158,7 +158,7 @@ void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, dou
 // matrix-based path on structured lattices (csr.hip)
 int64_t csr_nnz(const mfsem_op& op);
 void csr_assemble(const mfsem_op& op, int64_t* row_ptr, int32_t* col, double* val, hipStream_t s);
-void csr_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+void csr_spmv(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col, const double* val,
               const double* x, double* y, hipStream_t s);
 
 // vector kernels (vec.hip)
