@@ -237,6 +237,40 @@ def cpu_baseline(spec, budget_s=20.0):
                        f"{os.cpu_count()} logical CPUs")}
 
 
+def cpu_pcg_baseline(spec, chain, degree, max_dofs=1_000_000):
+    """The oracle's GMG-PCG (explicit level matrices, prolongation matrices and
+    V-cycle, the same chain and Chebyshev degrees, lambda_max by its own 10-step
+    Lanczos) to 1e-10 from zero on the workload's right-hand side, timed on the
+    host beside the GPU solve.  Only for meshes the oracle assembles in seconds."""
+    import numpy as np
+    import synth
+    from oracle import multigrid as omg
+    from oracle import operator as oop
+    from oracle import solvers as osol
+    if spec.n_dof > max_dofs or spec.quad != "gll" or any(c[0] != "p" for c in chain):
+        return None
+    t0 = time.perf_counter()
+    mats, Ps, p = [oop.Problem(spec).assemble()[0]], [], spec.p
+    for c in chain:
+        mats.append(oop.Problem(spec, dof_p=c[1], quad="gll").assemble()[0])
+        Ps.append(omg.prolongation_p(spec.n, p, c[1]))
+        p = c[1]
+    levels = []
+    for A in mats:
+        dinv = 1.0 / A.diagonal()
+        levels.append((A, dinv, osol.lanczos_lambda_max(A, dinv, synth.uniform(7, A.shape[0]))))
+    t_setup = time.perf_counter() - t0
+    f = synth.uniform(2, spec.n_dof)
+    t1 = time.perf_counter()
+    x, it, rn = osol.cg(mats[0], f, rtol=1e-10,
+                        M=lambda r: osol.vcycle(levels, Ps, r, degree, 2 * degree))
+    t_solve = time.perf_counter() - t1
+    return {"kind": "oracle", "cores": 1, "time_to_1e-10_ms": round(t_solve * 1e3, 1),
+            "iterations": it, "setup_s": round(t_setup, 1),
+            "sample": "oracle GMG-PCG with explicit SciPy level matrices (same chain, Chebyshev "
+                      "degree, tolerance and right-hand side), one thread"}
+
+
 def matrix_based(mf, op, x, t_mf_ms, spec, max_bytes=40e9):
     """The paper's matrix-based comparison on the GPU: assemble A in CSR
     (mfsem_csr_assemble) and time its product (mfsem_csr_spmv) beside the
@@ -516,6 +550,10 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(spec)
+        if kind == "pcg":
+            pcg_cpu = cpu_pcg_baseline(spec, coarsening, cheb_degree)
+            if pcg_cpu is not None:
+                out["cpu_baseline"]["pcg"] = pcg_cpu
     print(json.dumps(out), flush=True)
 
 
