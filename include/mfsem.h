@@ -248,8 +248,12 @@ mfsem_status mfsem_csr_spmv(int64_t n_rows, int64_t nnz, const int64_t* row_ptr,
  * valid CG preconditioner.  Every level must hold geometry in `precision`.  */
 typedef struct {
   int32_t kind;             /* mfsem_transfer_kind */
-  const int32_t* parent;    /* H: [device] [n_elem_fine]; P: NULL */
-  const int8_t* child;      /* H: [device] [n_elem_fine]; P: NULL */
+  const int32_t* parent;    /* H: [device] [n_elem_fine], coarse element of each fine
+                               element (0 <= parent < n_elem_coarse); P: NULL */
+  const int8_t* child;      /* H: [device] [n_elem_fine], octant cx + 2 cy + 4 cz of the
+                               fine element in its parent's local axes; P: NULL.
+                               mfsem_mg_create checks both ranges on the device
+                               (EINVAL naming the level).                        */
 } mfsem_transfer_desc;
 
 typedef struct {

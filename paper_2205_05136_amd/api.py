@@ -257,6 +257,12 @@ class Multigrid:
                 trs[i] = L.TransferDesc(kind=L.MFSEM_TRANSFER_P, parent=None, child=None)
             else:
                 parent, child = t[1], t[2]
+                nf = self.ops[i].n_elem
+                if (parent.dtype != torch.int32 or child.dtype != torch.int8 or not parent.is_cuda
+                        or not child.is_cuda or parent.numel() != nf or child.numel() != nf
+                        or not parent.is_contiguous() or not child.is_contiguous()):
+                    raise ValueError(f"h-transfer {i}: parent (int32) and child (int8) need "
+                                     f"{nf} contiguous CUDA entries")
                 self._keep += [parent, child]
                 trs[i] = L.TransferDesc(kind=L.MFSEM_TRANSFER_H, parent=parent.data_ptr(),
                                         child=child.data_ptr())

@@ -283,6 +283,20 @@ void mg_setup(mfsem_mg& mg, hipStream_t s) {
       launch_diag<float>(*L.op, P_<float>(L.dinv), s);
       vinvert<float>(P_<float>(L.dinv), L.n * B, s);
     }
+    if (l + 1 < mg.lv.size() && L.tr.kind == MFSEM_TRANSFER_H) {
+      // parent/child arrays index the coarse elements and the child halves: an
+      // out-of-range entry would make the transfer kernels read out of bounds
+      auto* bad = reinterpret_cast<unsigned long long*>(mg.scratch);
+      MFSEM_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), s));
+      launch_parents_range_check(L.op->d.n_elem, mg.lv[l + 1].op->d.n_elem, L.tr.parent,
+                                 L.tr.child, bad, s);
+      unsigned long long nbad = 0;
+      MFSEM_HIP(hipMemcpyAsync(&nbad, bad, sizeof(nbad), hipMemcpyDeviceToHost, s));
+      MFSEM_HIP(hipStreamSynchronize(s));
+      if (nbad != 0)
+        fail(MFSEM_EINVAL, "h-transfer of level " + std::to_string(l) + ": " +
+                               std::to_string(nbad) + " parent/child entries out of range");
+    }
     if (l + 1 < mg.lv.size() && L.lattice && L.tr.kind == MFSEM_TRANSFER_H) {
       auto* mismatch = reinterpret_cast<unsigned long long*>(mg.scratch);
       MFSEM_HIP(hipMemsetAsync(mismatch, 0, sizeof(unsigned long long), s));

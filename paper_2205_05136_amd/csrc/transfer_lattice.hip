@@ -99,6 +99,17 @@ __global__ void box_parents_check_kernel(int n0, int n1, int64_t n_elem,
   if (bad) atomicAdd(mismatch, bad);
 }
 
+__global__ void parents_range_kernel(int64_t n_fine, int64_t n_coarse,
+                                     const int32_t* __restrict__ parent,
+                                     const int8_t* __restrict__ child,
+                                     unsigned long long* __restrict__ bad) {
+  unsigned long long cnt = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_fine;
+       e += (int64_t)gridDim.x * blockDim.x)
+    cnt += (parent[e] < 0 || parent[e] >= n_coarse || child[e] < 0 || child[e] > 7) ? 1 : 0;
+  if (cnt) atomicAdd(bad, cnt);
+}
+
 // 1D tables of one axis: forward (per fine node: first coarse node and Pc
 // coefficients) and transposed (per coarse node: fine nodes and coefficients).
 void build_axis(int kind, int pf, int pc, int nf_elem, const std::vector<double>& I,
@@ -200,6 +211,15 @@ void launch_box_parents_check(const int32_t n_fine[3], const int32_t* parent,
   box_parents_check_kernel<<<(unsigned)blocks, 256, 0, s>>>(n_fine[0], n_fine[1], ne, parent,
                                                            child, mismatch);
   MFSEM_LAUNCH("box_parents_check_kernel");
+}
+
+void launch_parents_range_check(int64_t n_fine, int64_t n_coarse, const int32_t* parent,
+                                const int8_t* child, unsigned long long* bad, hipStream_t s) {
+  if (n_fine == 0) return;
+  int64_t blocks = (n_fine + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  parents_range_kernel<<<(unsigned)blocks, 256, 0, s>>>(n_fine, n_coarse, parent, child, bad);
+  MFSEM_LAUNCH("parents_range_kernel");
 }
 
 // x pass, y pass, z pass: (ncx, ncy, ncz) -> (nfx, ncy, ncz) -> (nfx, nfy, ncz)

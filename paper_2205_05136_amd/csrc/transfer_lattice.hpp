@@ -43,6 +43,11 @@ void lattice_transfer_upload(const LatticeTransfer& t);
 void launch_box_parents_check(const int32_t n_fine[3], const int32_t* parent,
                               const int8_t* child, unsigned long long* mismatch, hipStream_t s);
 
+// Adds to *bad the fine elements whose parent is outside [0, n_coarse) or whose
+// child index is outside 0..7.
+void launch_parents_range_check(int64_t n_fine, int64_t n_coarse, const int32_t* parent,
+                                const int8_t* child, unsigned long long* bad, hipStream_t s);
+
 // xf = P xc, or xf += P xc with accumulate; with zero_f, zero_f[i] = 0 at
 // every fine node as well.
 template <typename T>

@@ -1,5 +1,7 @@
 """Conforming hexahedral meshes given by arrays instead of the box generator:
-element orientation, element and node renumbering, and locality ordering.
+element orientation, element and node renumbering, locality ordering, octree
+refinement of an arbitrary coarse mesh (the h-levels of the multigrid,
+Section 4.3) and the degree-p node maps of its elements (the p-levels).
 
 The operator takes any conforming element-to-node map (Section 3: the Q_p
 space on a conforming hexahedral mesh) with the general element kernel
@@ -128,3 +130,181 @@ def to_mesh(p: int, elem_dof: np.ndarray, xyz: np.ndarray, fiber: np.ndarray | N
                 xyz=torch.as_tensor(xyz, dtype=torch.float64, device=dev).contiguous(),
                 fiber=None if fiber is None else
                 torch.as_tensor(fiber, dtype=torch.float64, device=dev).contiguous())
+
+
+# ------------------------------------------------------------------------------
+# Node lattices on arbitrary conforming meshes: octree refinement and p-levels.
+#
+# A node of an element's m-subdivision lattice (local indices I, J, K in 0..m)
+# lies in the interior of the element, of one of its faces or edges, or at a
+# corner.  Nodes shared by several elements are identified topologically, from
+# the global ids of the corners of that face, edge or corner: the anchor is the
+# corner with the smallest id, the face's two directions are ordered by the ids
+# of the anchor's neighbours along them, and the node's position is its index
+# distance from the anchor along each direction.  Every element sharing the
+# entity computes the same key (the lattices are symmetric: GLL points and the
+# halves of the octree children), so the numbering needs no coordinates.
+
+def gll_points(p: int) -> np.ndarray:
+    """The p+1 Gauss-Lobatto-Legendre points on [-1, 1] (ends and the roots of P_p')."""
+    if p == 1:
+        return np.array([-1.0, 1.0])
+    from numpy.polynomial import legendre as L
+    inner = np.sort(L.legroots(L.legder(np.eye(p + 1)[p])).real)
+    # one Newton step on P_p' for full accuracy
+    d1, d2 = L.legder(np.eye(p + 1)[p]), L.legder(np.eye(p + 1)[p], 2)
+    inner = inner - L.legval(inner, d1) / L.legval(inner, d2)
+    return np.concatenate([[-1.0], inner, [1.0]])
+
+
+def lagrange_1d(nodes: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """[len(pts)][len(nodes)]: the nodal Lagrange basis at the points."""
+    out = np.ones((len(pts), len(nodes)))
+    for j, xj in enumerate(nodes):
+        for m, xm in enumerate(nodes):
+            if m != j:
+                out[:, j] *= (pts - xm) / (xj - xm)
+    return out
+
+
+def element_corners(elem_dof: np.ndarray, p: int) -> np.ndarray:
+    """Global ids of each element's 8 corner nodes, [n_elem][8], corner
+    (sx, sy, sz) in {0, 1}^3 at column sx + 2 sy + 4 sz."""
+    P = p + 1
+    cols = [(sx * p) + P * ((sy * p) + P * (sz * p))
+            for sz in (0, 1) for sy in (0, 1) for sx in (0, 1)]
+    return np.asarray(elem_dof)[:, cols]
+
+
+def lattice_numbering(corners: np.ndarray, m: int):
+    """Global numbering of every element's (m+1)^3 lattice nodes, shared nodes
+    identified through the corner ids.  corners [n_elem][8] (element_corners).
+    Returns (ids [n_elem][(m+1)^3] with local index I + (m+1)(J + (m+1)K),
+    n_nodes, first) where first[g] = (element, local index) of node g's first
+    occurrence."""
+    corners = np.asarray(corners, dtype=np.int64)
+    ne = corners.shape[0]
+    M = m + 1
+    keys = np.zeros((ne, M ** 3, 7), dtype=np.int64)
+    erange = np.arange(ne)
+    for K in range(M):
+        for J in range(M):
+            for I in range(M):
+                loc = I + M * (J + M * K)
+                idx = (I, J, K)
+                side = [0 if v == 0 else (1 if v == m else -1) for v in idx]
+                free = [ax for ax in range(3) if side[ax] < 0]
+                if len(free) == 3:
+                    keys[:, loc, 0] = 3
+                    keys[:, loc, 1] = erange
+                    keys[:, loc, 2:5] = idx
+                    continue
+                # corners of the entity: the free axes take both sides
+                combos = []
+                for bits in range(1 << len(free)):
+                    sd = list(side)
+                    for k, ax in enumerate(free):
+                        sd[ax] = (bits >> k) & 1
+                    combos.append(sd[0] + 2 * sd[1] + 4 * sd[2])
+                C = corners[:, combos]                          # [ne][2^d]
+                amin = np.argmin(C, axis=1)
+                v0 = C[erange, amin]
+                keys[:, loc, 0] = len(free)
+                keys[:, loc, 1] = v0
+                if not free:
+                    continue
+                # the anchor's side on each free axis, its neighbours and distances
+                nb, dist = [], []
+                for k, ax in enumerate(free):
+                    s0 = (amin >> k) & 1                       # anchor side on this axis
+                    nb.append(C[erange, amin ^ (1 << k)])
+                    dist.append(np.where(s0 == 0, idx[ax], m - idx[ax]))
+                if len(free) == 1:
+                    keys[:, loc, 2] = nb[0]
+                    keys[:, loc, 3] = dist[0]
+                else:
+                    swap = nb[1] < nb[0]
+                    keys[:, loc, 2] = np.where(swap, nb[1], nb[0])
+                    keys[:, loc, 3] = np.where(swap, nb[0], nb[1])
+                    keys[:, loc, 4] = np.where(swap, dist[1], dist[0])
+                    keys[:, loc, 5] = np.where(swap, dist[0], dist[1])
+    flat = keys.reshape(-1, 7)
+    _, first, inv = np.unique(flat, axis=0, return_index=True, return_inverse=True)
+    ids = inv.reshape(ne, M ** 3)
+    # number the nodes by first appearance (element order), not by key order
+    order = np.argsort(first, kind="stable")
+    renum = np.empty_like(order)
+    renum[order] = np.arange(len(order))
+    ids = renum[ids]
+    first = first[order]
+    return ids, len(order), np.stack([first // M ** 3, first % M ** 3], axis=1)
+
+
+def _map_at(mesh_p: int, elem_dof: np.ndarray, values: np.ndarray, elems: np.ndarray,
+            xi: np.ndarray, I: np.ndarray, J: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """Interpolate a nodal field of degree mesh_p at reference points: for each
+    (elems[n], xi[I[n]], xi[J[n]], xi[K[n]]), sum_abc v[node abc] l_a l_b l_c."""
+    P = mesh_p + 1
+    Lm = lagrange_1d(gll_points(mesh_p), xi)                    # [len(xi)][P]
+    v = values[np.asarray(elem_dof)[elems]].reshape(len(elems), P, P, P, -1)  # [n][c][b][a][d]
+    return np.einsum("na,nb,nc,ncbad->nd", Lm[I], Lm[J], Lm[K], v)
+
+
+def refine(mesh: "Mesh | tuple"):
+    """Octree refinement of a conforming mesh: every element split into its 8
+    children, the children's degree-p nodes numbered once across the mesh, and
+    node coordinates and fibers interpolated from the parent's map (exact: the
+    parent's degree-p map restricted to a child is a degree-p polynomial of the
+    child's reference coordinates, Section 4.3).  Accepts a Mesh (moved to the
+    host) or (p, elem_dof, xyz, fiber) numpy arrays.  Returns
+    (p, elem_dof, xyz, fiber, parent, child) as numpy arrays: fine element
+    8 e + c is child c = cx + 2 cy + 4 cz of coarse element e, with its local
+    axes those of the parent (the convention of the h-transfer)."""
+    p, ed, xyz, fib = _arrays(mesh)
+    ne, P = ed.shape[0], p + 1
+    m = 2 * p
+    ids, n_nodes, first = lattice_numbering(element_corners(ed, p), m)
+    M = m + 1
+    # fine element (e, c) node (a, b, cc) -> lattice (cx p + a, cy p + b, cz p + cc)
+    a = np.arange(P)
+    A, B, Cc = np.meshgrid(a, a, a, indexing="ij")
+    A, B, Cc = (v.transpose(2, 1, 0).reshape(-1) for v in (A, B, Cc))  # local a + P(b + P c)
+    fine_ed = np.empty((ne * 8, P ** 3), dtype=np.int64)
+    for c in range(8):
+        cx, cy, cz = c & 1, (c >> 1) & 1, (c >> 2) & 1
+        loc = (cx * p + A) + M * ((cy * p + B) + M * (cz * p + Cc))
+        fine_ed[c::8] = ids[:, loc]
+    parent = np.repeat(np.arange(ne), 8)
+    child = np.tile(np.arange(8), ne)
+    # coordinates at the lattice positions of the first occurrence of each node
+    x = gll_points(p)
+    lat = np.concatenate([(x[:-1] - 1.0) / 2.0, (x + 1.0) / 2.0])   # 2p+1 points on [-1, 1]
+    e0, l0 = first[:, 0], first[:, 1]
+    I, J, K = l0 % M, (l0 // M) % M, l0 // (M * M)
+    xyz_f = _map_at(p, ed, xyz, e0, lat, I, J, K)
+    fib_f = None if fib is None else _map_at(p, ed, fib, e0, lat, I, J, K)
+    return p, fine_ed, xyz_f, fib_f, parent, child
+
+
+def degree_mesh(mesh: "Mesh | tuple", pc: int):
+    """The degree-pc node map of the same elements (a p-level of the multigrid
+    on an arbitrary mesh), nodes numbered once across the mesh and placed by the
+    degree-p map.  Returns (pc, elem_dof, xyz, fiber) as numpy arrays."""
+    p, ed, xyz, fib = _arrays(mesh)
+    ids, n_nodes, first = lattice_numbering(element_corners(ed, p), pc)
+    M = pc + 1
+    e0, l0 = first[:, 0], first[:, 1]
+    I, J, K = l0 % M, (l0 // M) % M, l0 // (M * M)
+    xc = gll_points(pc)
+    xyz_c = _map_at(p, ed, xyz, e0, xc, I, J, K)
+    fib_c = None if fib is None else _map_at(p, ed, fib, e0, xc, I, J, K)
+    return pc, ids, xyz_c, fib_c
+
+
+def _arrays(mesh):
+    if isinstance(mesh, Mesh):
+        return (mesh.p, mesh.elem_dof.cpu().numpy().astype(np.int64),
+                mesh.xyz.cpu().numpy(), None if mesh.fiber is None else mesh.fiber.cpu().numpy())
+    p, ed, xyz, fib = mesh
+    return p, np.asarray(ed, dtype=np.int64), np.asarray(xyz, dtype=np.float64), (
+        None if fib is None else np.asarray(fib, dtype=np.float64))

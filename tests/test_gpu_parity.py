@@ -528,3 +528,13 @@ def test_error_paths():
         op.apply(torch.zeros(3, device="cuda", dtype=torch.float64))
     with pytest.raises(mf.MfsemError):
         op.apply(torch.zeros(spec.n_dof, device="cuda", dtype=torch.float32))  # no FP32 geometry
+    # h-transfer arrays are range-checked on the device before any transfer uses them
+    coarse = mf.Operator.from_spec(spec.with_(n=(1, 1, 1)))
+    par, chi = mf.box_parents(spec.n)
+    for bad_par, bad_chi in ((par + 1, chi), (par, chi + 8)):
+        with pytest.raises(mf.MfsemError) as e:
+            mf.Multigrid([op, coarse], [("h", bad_par.contiguous(), bad_chi.contiguous())],
+                         lambda_max=[1.0, 1.0])
+        assert e.value.status == -1 and "out of range" in str(e.value)
+    with pytest.raises(ValueError):
+        mf.Multigrid([op, coarse], [("h", par.long(), chi)], lambda_max=[1.0, 1.0])

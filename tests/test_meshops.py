@@ -121,3 +121,163 @@ def test_general_kernel_and_pmg_on_a_scrambled_mesh():
     u_ref = spla.spsolve(A.tocsc(), f)
     assert rel_l2(to_np(u)[node_perm], u_ref) <= 1e-11
     assert info.iters[0] <= 25
+
+
+# ------------------------------------------------------- refinement / p-levels
+# An unsheared box with a uniform fiber: its geometry and fibers are polynomial,
+# so the refined mesh is exactly the box at twice the elements.
+BOX = synth.BoxSpec(p=3, n=(2, 2, 1), length=(2.0, 1.6, 1.0), fiber=True, theta0=0.6,
+                    theta1=0.6, sigma=(0.17, 0.05, 0.05), alpha=3.0)
+
+
+def _struct_elem(spec, ex, ey, ez):
+    return ex + spec.n[0] * (ey + spec.n[1] * ez)
+
+
+def test_lattice_numbering_counts_on_a_box():
+    from oracle import mesh as omesh
+    m = omesh.box(BOX)
+    for sub in (1, 2, 3, 6):
+        ids, n, first = meshops.lattice_numbering(meshops.element_corners(m.elem_dof, BOX.p), sub)
+        assert n == np.prod([sub * k + 1 for k in BOX.n])
+        assert ids.max() == n - 1 and np.array_equal(np.unique(ids), np.arange(n))
+        # the first occurrence of node g is an element that holds it there
+        assert np.array_equal(ids[first[:, 0], first[:, 1]], np.arange(n))
+
+
+def test_refined_box_is_the_box_at_twice_the_elements():
+    from oracle import mesh as omesh
+    m = omesh.box(BOX)
+    p, ed, xyz, fib, parent, child = meshops.refine((BOX.p, m.elem_dof, m.xyz, m.fiber))
+    fine = BOX.with_(n=tuple(2 * k for k in BOX.n))
+    mf_ = omesh.box(fine)
+    assert xyz.shape[0] == fine.n_dof and ed.shape[0] == fine.n_elem
+    for e in range(BOX.n_elem):
+        ex, ey, ez = e % BOX.n[0], (e // BOX.n[0]) % BOX.n[1], e // (BOX.n[0] * BOX.n[1])
+        for c in range(8):
+            f = 8 * e + c
+            assert parent[f] == e and child[f] == c
+            s = _struct_elem(fine, 2 * ex + (c & 1), 2 * ey + ((c >> 1) & 1), 2 * ez + (c >> 2))
+            np.testing.assert_allclose(xyz[ed[f]], mf_.xyz[mf_.elem_dof[s]], atol=1e-14)
+            np.testing.assert_allclose(fib[ed[f]], mf_.fiber[mf_.elem_dof[s]], atol=1e-14)
+
+
+def _scrambled_coarse(spec, seed):
+    from oracle import mesh as omesh
+    m = omesh.box(spec)
+    rng = np.random.default_rng(seed)
+    rot = rng.integers(0, 24, spec.n_elem)
+    ed = meshops.reorient(m.elem_dof, spec.p, rot)
+    return meshops.permute(ed, m.xyz, m.fiber, rng.permutation(spec.n_dof),
+                           rng.permutation(spec.n_elem))
+
+
+def _match(xyz_a, xyz_b):
+    """perm with xyz_a[perm] == xyz_b (nodes matched by coordinates)."""
+    ka = np.round(xyz_a / 1e-9).astype(np.int64)
+    kb = np.round(xyz_b / 1e-9).astype(np.int64)
+    ia = np.lexsort(ka.T[::-1])
+    ib = np.lexsort(kb.T[::-1])
+    assert np.array_equal(ka[ia], kb[ib])
+    perm = np.empty(len(ib), dtype=np.int64)
+    perm[ib] = ia
+    return perm
+
+
+def _h_prolongation(p, ed_f, ed_c, parent, child, n_f, n_c):
+    """Element-wise interpolation from each parent at its child's nodes."""
+    from oracle import basis, quadrature
+    x, _ = quadrature.gll(p)
+    half = [basis.lagrange(x, (x + 2 * c - 1) / 2.0) for c in (0, 1)]
+    Pm = np.zeros((n_f, n_c))
+    for f in range(ed_f.shape[0]):
+        c = child[f]
+        I3 = basis.tensor3(half[c & 1], half[(c >> 1) & 1], half[(c >> 2) & 1])
+        Pm[np.ix_(ed_f[f], ed_c[parent[f]])] = I3
+    return Pm
+
+
+def test_refined_scrambled_mesh_operator_and_h_prolongation():
+    """Refining a rotated, shuffled, renumbered coarse box gives the permuted
+    operator of the box at twice the elements, and its parent/child maps give
+    the permuted octree prolongation."""
+    from oracle import multigrid as omg
+    ced, cxyz, cfib = _scrambled_coarse(BOX, 11)
+    p, ed, xyz, fib, parent, child = meshops.refine((BOX.p, ced, cxyz, cfib))
+    fine = BOX.with_(n=tuple(2 * k for k in BOX.n))
+    prob = oop.Problem(fine)
+    A = prob.assemble()[0]
+    pf = _match(xyz, prob.mesh.xyz)            # xyz[pf] = structured node order
+    Au = _assemble(prob, fine, ed, xyz, fib, np.broadcast_to(prob.sigma[0], (fine.n_elem, 3)))
+    Pf = sp.csr_matrix((np.ones(fine.n_dof), (pf, np.arange(fine.n_dof))), shape=(fine.n_dof,) * 2)
+    assert abs(Au - Pf @ A @ Pf.T).max() <= 1e-13 * abs(A).max()
+    from oracle import mesh as omesh
+    pc = _match(cxyz, omesh.box(BOX).xyz)
+    Pu = _h_prolongation(p, ed, ced, parent, child, fine.n_dof, BOX.n_dof)
+    Ps = omg.prolongation_h(fine.n, p).toarray()
+    np.testing.assert_allclose(Pu[np.ix_(pf, pc)], Ps, atol=1e-14)
+
+
+def test_degree_mesh_is_the_lower_degree_box():
+    from oracle import mesh as omesh
+    ced, cxyz, cfib = _scrambled_coarse(BOX, 12)
+    for pc in (1, 2):
+        q, ed, xyz, fib = meshops.degree_mesh((BOX.p, ced, cxyz, cfib), pc)
+        box_c = omesh.box(BOX.with_(p=pc))
+        assert xyz.shape[0] == box_c.xyz.shape[0]
+        _match(xyz, box_c.xyz)
+        # each element's degree-pc nodes sit at its degree-p map's GLL(pc) points
+        assert np.array_equal(np.unique(ed), np.arange(xyz.shape[0]))
+        corners_p = meshops.element_corners(ced, BOX.p)
+        corners_c = meshops.element_corners(ed, pc)
+        np.testing.assert_allclose(cxyz[corners_p], xyz[corners_c], atol=1e-14)
+
+
+@pytest.mark.gpu
+def test_hp_multigrid_on_a_refined_scrambled_mesh():
+    """Octree h-level and p-level built from arrays (refine, degree_mesh) on an
+    unstructured mesh: the h-prolongation equals the permuted oracle's and the
+    h+p multigrid PCG solves the permuted oracle system."""
+    import torch
+    import paper_2205_05136_amd as mf
+    from gpu_common import announce, rel_l2, to_dev, to_np
+    from oracle import mesh as omesh
+    from oracle import multigrid as omg
+    import scipy.sparse.linalg as spla
+    announce("refined scrambled mesh h+p multigrid")
+    spec = BOX.with_(n=(4, 2, 2))
+    ced, cxyz, cfib = _scrambled_coarse(spec, 13)
+    p, ed, xyz, fib, parent, child = meshops.refine((spec.p, ced, cxyz, cfib))
+    fine = spec.with_(n=tuple(2 * k for k in spec.n))
+    prob = oop.Problem(fine)
+    A = prob.assemble()[0]
+    pf = _match(xyz, prob.mesh.xyz)
+    pc = _match(cxyz, omesh.box(spec).xyz)
+    kw = dict(sigma_const=spec.sigma, alpha=spec.alpha, structured=False)
+    m_f = meshops.to_mesh(p, ed, xyz, fib)
+    m_c = meshops.to_mesh(p, ced, cxyz, cfib)
+    q, ed1, xyz1, fib1 = meshops.degree_mesh((spec.p, ced, cxyz, cfib), 1)
+    m_1 = meshops.to_mesh(1, ed1, xyz1, fib1)
+    ops = [mf.Operator(m_f, **kw), mf.Operator(m_c, **kw), mf.Operator(m_1, geometry=m_c, **kw)]
+    par = torch.as_tensor(parent.astype(np.int32), device="cuda")
+    chi = torch.as_tensor(child.astype(np.int8), device="cuda")
+    mg = mf.Multigrid(ops, [("h", par, chi), ("p",)], degree=3)
+    # h-prolongation against the oracle's, permuted
+    Ps = omg.prolongation_h(fine.n, p)
+    xc = synth.uniform(120, spec.n_dof)
+    xcu = np.empty_like(xc)
+    xcu[pc] = xc
+    yu = to_np(mg.prolong(0, to_dev(xcu)))
+    assert rel_l2(yu[pf], Ps @ xc) <= 1e-12
+    # the fine operator and the solve
+    x = synth.uniform(121, fine.n_dof)
+    xu = np.empty_like(x)
+    xu[pf] = x
+    assert rel_l2(to_np(ops[0].apply(to_dev(xu)))[pf], A @ x) <= 1e-12
+    f = synth.uniform(122, fine.n_dof)
+    fu = np.empty_like(f)
+    fu[pf] = f
+    u, info = mf.pcg(ops[0], to_dev(fu), mg=mg, rtol=1e-12, max_it=100)
+    u_ref = spla.spsolve(A.tocsc(), f)
+    assert rel_l2(to_np(u)[pf], u_ref) <= 1e-10
+    assert info.iters[0] <= 20, info.iters
