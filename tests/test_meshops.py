@@ -281,3 +281,27 @@ def test_hp_multigrid_on_a_refined_scrambled_mesh():
     u_ref = spla.spsolve(A.tocsc(), f)
     assert rel_l2(to_np(u)[pf], u_ref) <= 1e-10
     assert info.iters[0] <= 20, info.iters
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_refine_and_degree_mesh_on_random_scrambled_boxes(seed):
+    """Random box sizes, degrees and scramblings: the refined mesh and the
+    degree-pc mesh have the structured node counts and node positions."""
+    from oracle import mesh as omesh
+    rng = np.random.default_rng(100 + seed)
+    p = int(rng.integers(1, 5))
+    n = tuple(int(v) for v in rng.integers(1, 4, 3))
+    spec = synth.BoxSpec(p=p, n=n, length=tuple(rng.uniform(0.5, 2.0, 3)), fiber=True,
+                         theta0=0.3, theta1=0.3)
+    ced, cxyz, cfib = _scrambled_coarse(spec, 200 + seed)
+    q, ed, xyz, fib, parent, child = meshops.refine((p, ced, cxyz, cfib))
+    fine = omesh.box(spec.with_(n=tuple(2 * k for k in n)))
+    assert xyz.shape[0] == fine.xyz.shape[0] and ed.shape[0] == 8 * spec.n_elem
+    _match(xyz, fine.xyz)
+    # every fine element's nodes lie inside its parent's bounding box
+    lo = cxyz[ced].min(axis=1)[parent] - 1e-12
+    hi = cxyz[ced].max(axis=1)[parent] + 1e-12
+    assert np.all((xyz[ed] >= lo[:, None, :]) & (xyz[ed] <= hi[:, None, :]))
+    pc = int(rng.integers(1, p + 1))
+    _, ed_c, xyz_c, _ = meshops.degree_mesh((p, ced, cxyz, cfib), pc)
+    _match(xyz_c, omesh.box(spec.with_(p=pc)).xyz)
