@@ -459,8 +459,12 @@ void dispatch(const mfsem_op& op, const T* x, T* y, T alpha, hipStream_t s) {
 // ------------------------------------------------------------ diagonal -----
 // diag(A)_i = sum_e sum_k [alpha W|J| phi_i^2 + grad_ref(phi_i)^T G grad_ref(phi_i)],
 // with phi_i = l_a l_b l_c and grad_ref = (l_a' l_b l_c, l_a l_b' l_c, l_a l_b l_c').
-// One workgroup per element; each of the 7 stored fields is staged in LDS in
-// turn and every lane accumulates its nodes' sums over all quadrature points.
+// Each of the seven stored fields F (alpha W|J| and the six entries of G) is
+// weighted by a product of 1D factors, e.g. G00 by (l_a')^2 (l_b)^2 (l_c)^2 and
+// G01 by 2 (l_a l_a')(l_b l_b')(l_c)^2, so its contribution is the separable
+// contraction sum_k3 Z[k3][c] sum_k2 Y[k2][b] sum_k1 X[k1][a] F[k3][k2][k1],
+// evaluated as three 1D passes (sum factorisation, Section 4.1) with X, Y, Z
+// among BB = B^2, DD = D^2, BD = B D.  One workgroup per element and member.
 constexpr int DIAG_THREADS = 256;
 constexpr int MAXQ = MFSEM_MAX_P + 3, MAXP = MFSEM_MAX_P + 1;
 
@@ -469,53 +473,62 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_kernel(
     int64_t n_elem, int64_t n_dof, int P, int Q, const int32_t* __restrict__ ed,
     const T* __restrict__ G, const T* __restrict__ WJ, T alpha, const T* __restrict__ Btab,
     const T* __restrict__ Dbtab, T* __restrict__ d) {
-  __shared__ T sB[MAXQ * MAXP], sD[MAXQ * MAXP];
+  __shared__ T sM[3][MAXQ * MAXP];  // BB, DD, BD
   __shared__ T sF[MAXQ * MAXQ * MAXQ];
+  __shared__ T t1[MAXQ * MAXQ * MAXP];
+  __shared__ T t2[MAXQ * MAXP * MAXP];
   const int64_t e = blockIdx.x;
   const int bt = blockIdx.y;
-  const int P3 = P * P * P, Q3 = Q * Q * Q;
+  const int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
   const int tid = threadIdx.x;
   for (int t = tid; t < Q * P; t += blockDim.x) {
-    sB[t] = Btab[t];
-    sD[t] = Dbtab[t];
+    const T b = Btab[t], dd = Dbtab[t];
+    sM[0][t] = b * b;
+    sM[1][t] = dd * dd;
+    sM[2][t] = b * dd;
   }
   constexpr int MAXN = (MAXP * MAXP * MAXP + DIAG_THREADS - 1) / DIAG_THREADS;
   T acc[MAXN];
   for (int r = 0; r < MAXN; ++r) acc[r] = 0;
   const T* Ge = G + ((int64_t)bt * n_elem + e) * 6 * Q3;
-  // field f: 0 = alpha*WJ, 1 = G00, 2 = G11, 3 = G22, 4 = G01, 5 = G02, 6 = G12
+  // field f: 0 = alpha*WJ, 1 = G00, 2 = G11, 3 = G22, 4 = G01, 5 = G02, 6 = G12,
+  // with its 1D factors along x, y, z (0 = BB, 1 = DD, 2 = BD) and multiplicity
   const int gidx[7] = {-1, 0, 3, 5, 1, 2, 4};
+  const int fx[7] = {0, 1, 0, 0, 2, 2, 0}, fy[7] = {0, 0, 1, 0, 2, 0, 2},
+            fz[7] = {0, 0, 0, 1, 0, 2, 2};
   for (int f = 0; f < 7; ++f) {
     __syncthreads();
     for (int k = tid; k < Q3; k += blockDim.x)
       sF[k] = (f == 0) ? alpha * WJ[e * Q3 + k] : Ge[(int64_t)k * 6 + gidx[f]];
     __syncthreads();
+    const T* X = sM[fx[f]];
+    const T* Y = sM[fy[f]];
+    const T* Z = sM[fz[f]];
+    const T mult = f >= 4 ? T(2) : T(1);
+    // x: t1[k3][k2][a] = sum_k1 X[k1][a] F[k3][k2][k1]
+    for (int l = tid; l < Q2 * P; l += blockDim.x) {
+      const int a = l % P, k23 = l / P;
+      T s = 0;
+      for (int k1 = 0; k1 < Q; ++k1) s += X[k1 * P + a] * sF[k23 * Q + k1];
+      t1[l] = s;
+    }
+    __syncthreads();
+    // y: t2[k3][b][a] = sum_k2 Y[k2][b] t1[k3][k2][a]
+    for (int l = tid; l < Q * P2; l += blockDim.x) {
+      const int a = l % P, b = (l / P) % P, k3 = l / P2;
+      T s = 0;
+      for (int k2 = 0; k2 < Q; ++k2) s += Y[k2 * P + b] * t1[(k3 * Q + k2) * P + a];
+      t2[l] = s;
+    }
+    __syncthreads();
+    // z: node (a, b, c) += mult sum_k3 Z[k3][c] t2[k3][b][a]
     for (int r = 0; r < MAXN; ++r) {
       const int l = tid + r * DIAG_THREADS;
       if (l >= P3) break;
-      const int a = l % P, b = (l / P) % P, c = l / (P * P);
+      const int ab = l % P2, c = l / P2;
       T s = 0;
-      for (int k3 = 0; k3 < Q; ++k3) {
-        const T Bz = sB[k3 * P + c], Dz = sD[k3 * P + c];
-        for (int k2 = 0; k2 < Q; ++k2) {
-          const T By = sB[k2 * P + b], Dy = sD[k2 * P + b];
-          for (int k1 = 0; k1 < Q; ++k1) {
-            const T Bx = sB[k1 * P + a], Dx = sD[k1 * P + a];
-            T w;
-            switch (f) {
-              case 0: w = Bx * By * Bz; w = w * w; break;
-              case 1: w = Dx * By * Bz; w = w * w; break;
-              case 2: w = Bx * Dy * Bz; w = w * w; break;
-              case 3: w = Bx * By * Dz; w = w * w; break;
-              case 4: w = T(2) * (Dx * By * Bz) * (Bx * Dy * Bz); break;
-              case 5: w = T(2) * (Dx * By * Bz) * (Bx * By * Dz); break;
-              default: w = T(2) * (Bx * Dy * Bz) * (Bx * By * Dz); break;
-            }
-            s += w * sF[k3 * Q * Q + k2 * Q + k1];
-          }
-        }
-      }
-      acc[r] += s;
+      for (int k3 = 0; k3 < Q; ++k3) s += Z[k3 * P + c] * t2[k3 * P2 + ab];
+      acc[r] += mult * s;
     }
   }
   for (int r = 0; r < MAXN; ++r) {

@@ -9,10 +9,15 @@
 // physical gradients grad = J^{-T} grad_ref.  This is the per-element
 // contraction of the adjoint method: dL/dsigma = -lambda^T (dA/dsigma) u.
 //
-// One workgroup per element; the geometry is recomputed from the map nodes
-// (as in the set-up kernel) and the reference gradients of u and w at each
-// quadrature point are direct sums over the element's nodes staged in LDS.
-// This runs once per gradient, not inside the solver loop.
+// One workgroup per element.  The geometry is recomputed from the map nodes
+// once per element, and the reference gradients of u and w of each batch
+// member at the quadrature points come from three 1D passes (sum
+// factorisation, Section 4.1) through LDS.  Per point the element keeps only
+// what the contraction needs: with v = sqrt(W|J|) J^{-1} a for a unit
+// direction a, (T_a grad w) . grad u = (v . grad_ref w)(v . grad_ref u), and
+// the isotropic part is grad_ref w^T (W|J| J^{-1} J^{-T}) grad_ref u.  When the
+// element's arrays do not fit the LDS budget (high p with Gauss points), a
+// direct-sum kernel (one point per lane, sums over all nodes) is used instead.
 #include "internal.hpp"
 
 namespace mfsem {
@@ -181,6 +186,222 @@ __global__ __launch_bounds__(GT) void grad_kernel(GradArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+constexpr int SFT = 256;
+constexpr size_t SF_LDS_MAX = 64 * 1024;
+
+// Reference gradient (and value) of a nodal field at the Q^3 points by three
+// 1D passes.  in: [P^3] nodal values, local index a + P (b + P c); B, D: [Q][P]
+// basis and derivative at the points; t1: [2][P P Q], t2: [3][P Q Q]; outputs
+// [Q^3] with point index k1 + Q (k2 + Q k3), each may be null.  Called by every
+// thread of the block; ends with a barrier.
+__device__ void sf_grad(const double* in, const double* B, const double* D, int P, int Q,
+                        double* t1, double* t2, double* d0, double* d1, double* d2,
+                        double* val) {
+  const int P2Q = P * P * Q, PQ2 = P * Q * Q, Q2 = Q * Q, Q3 = Q2 * Q;
+  // x: t1[0][c][b][k1] = sum_a B[k1][a] in[c][b][a], t1[1] with D
+  for (int l = threadIdx.x; l < P2Q; l += blockDim.x) {
+    const int k1 = l % Q, cb = l / Q;
+    double sb = 0, sd = 0;
+    for (int a = 0; a < P; ++a) {
+      const double v = in[cb * P + a];
+      sb += B[k1 * P + a] * v;
+      sd += D[k1 * P + a] * v;
+    }
+    t1[l] = sb;
+    t1[P2Q + l] = sd;
+  }
+  __syncthreads();
+  // y: t2[0] = B_y t1[0], t2[1] = D_y t1[0], t2[2] = B_y t1[1], as [c][k2][k1]
+  for (int l = threadIdx.x; l < PQ2; l += blockDim.x) {
+    const int k1 = l % Q, k2 = (l / Q) % Q, c = l / Q2;
+    double uu = 0, uy = 0, xd = 0;
+    for (int b = 0; b < P; ++b) {
+      const double vb = t1[(c * P + b) * Q + k1], vd = t1[P2Q + (c * P + b) * Q + k1];
+      uu += B[k2 * P + b] * vb;
+      uy += D[k2 * P + b] * vb;
+      xd += B[k2 * P + b] * vd;
+    }
+    t2[l] = uu;
+    t2[PQ2 + l] = uy;
+    t2[2 * PQ2 + l] = xd;
+  }
+  __syncthreads();
+  // z: d/dxi1 = B_z t2[2], d/dxi2 = B_z t2[1], d/dxi3 = D_z t2[0], value = B_z t2[0]
+  for (int l = threadIdx.x; l < Q3; l += blockDim.x) {
+    const int k12 = l % Q2, k3 = l / Q2;
+    double g0 = 0, g1 = 0, g2 = 0, v = 0;
+    for (int c = 0; c < P; ++c) {
+      const double bz = B[k3 * P + c], dz = D[k3 * P + c];
+      g0 += bz * t2[2 * PQ2 + c * Q2 + k12];
+      g1 += bz * t2[PQ2 + c * Q2 + k12];
+      g2 += dz * t2[c * Q2 + k12];
+      v += bz * t2[c * Q2 + k12];
+    }
+    if (d0) d0[l] = g0;
+    if (d1) d1[l] = g1;
+    if (d2) d2[l] = g2;
+    if (val) val[l] = v;
+  }
+  __syncthreads();
+}
+
+__host__ __device__ inline size_t sf_lds_doubles(int P, int Pm, int Q) {
+  const int PX = P > Pm ? P : Pm;
+  const int P3 = P * P * P, Pm3 = Pm * Pm * Pm, Q3 = Q * Q * Q;
+  return (size_t)2 * Q * P + 2 * Q * Pm + Q + (P3 > Pm3 ? P3 : Pm3) + 2 * PX * PX * Q +
+         3 * PX * Q * Q + 15 * Q3 + SFT / 64;
+}
+
+__global__ __launch_bounds__(SFT) void grad_sf_kernel(GradArgs a) {
+  extern __shared__ double lds[];
+  const int P = a.P, Pm = a.Pm, Q = a.Q;
+  const int PX = P > Pm ? P : Pm;
+  const int P3 = P * P * P, Pm3 = Pm * Pm * Pm, Q3 = Q * Q * Q;
+  double* sB = lds;
+  double* sD = sB + Q * P;
+  double* sBm = sD + Q * P;
+  double* sDm = sBm + Q * Pm;
+  double* sw = sDm + Q * Pm;
+  double* fld = sw + Q;
+  double* t1 = fld + (P3 > Pm3 ? P3 : Pm3);
+  double* t2 = t1 + 2 * PX * PX * Q;
+  double* geo = t2 + 3 * PX * Q * Q;  // [15][Q3]
+  double* sh = geo + 15 * Q3;
+  const int64_t e = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < Q * P; i += SFT) {
+    sB[i] = a.tab[a.oB + i];
+    sD[i] = a.tab[a.oDb + i];
+  }
+  for (int i = tid; i < Q * Pm; i += SFT) {
+    sBm[i] = a.tab[a.oBm + i];
+    sDm[i] = a.tab[a.oDm + i];
+  }
+  for (int i = tid; i < Q; i += SFT) sw[i] = a.tab[a.ow + i];
+
+  // geometry: J[r][s] in slots 3r + s, fiber in 9..11, sheet in 12..14
+  const int32_t* med = a.map_ed + e * Pm3;
+  for (int r = 0; r < 3; ++r) {
+    __syncthreads();
+    for (int i = tid; i < Pm3; i += SFT) fld[i] = a.xyz[(int64_t)med[i] * 3 + r];
+    __syncthreads();
+    sf_grad(fld, sBm, sDm, Pm, Q, t1, t2, geo + (3 * r) * Q3, geo + (3 * r + 1) * Q3,
+            geo + (3 * r + 2) * Q3, nullptr);
+  }
+  for (int r = 0; r < 3 && a.fiber; ++r) {
+    for (int i = tid; i < Pm3; i += SFT) fld[i] = a.fiber[(int64_t)med[i] * 3 + r];
+    __syncthreads();
+    sf_grad(fld, sBm, sDm, Pm, Q, t1, t2, nullptr, nullptr, nullptr, geo + (9 + r) * Q3);
+  }
+  for (int r = 0; r < 3 && a.sheet; ++r) {
+    for (int i = tid; i < Pm3; i += SFT) fld[i] = a.sheet[(int64_t)med[i] * 3 + r];
+    __syncthreads();
+    sf_grad(fld, sBm, sDm, Pm, Q, t1, t2, nullptr, nullptr, nullptr, geo + (12 + r) * Q3);
+  }
+  // per point, in place: slots 0..2 v_f, 3..5 v_s, 6..8 v_n (fiber and sheet);
+  // 0..2 v_f and 3..8 H = W|J| J^{-1} J^{-T} (fiber only); 3..8 H (no fiber)
+  for (int k = tid; k < Q3; k += SFT) {
+    double J[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) J[r][c] = geo[(3 * r + c) * Q3 + k];
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double id = 1.0 / det;
+    double Ji[3][3];
+    Ji[0][0] = c00 * id;
+    Ji[1][0] = c01 * id;
+    Ji[2][0] = c02 * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    const int k1 = k % Q, k2 = (k / Q) % Q, k3 = k / (Q * Q);
+    const double wj = sw[k1] * sw[k2] * sw[k3] * det;
+    const double rw = sqrt(wj);
+    // v[s] = sum_r Ji[s][r] a[r]: (J^{-T} grad_ref) . a = grad_ref . v
+    auto put_v = [&](const double* dir, int slot) {
+      for (int s_ = 0; s_ < 3; ++s_)
+        geo[(slot + s_) * Q3 + k] =
+            rw * (Ji[s_][0] * dir[0] + Ji[s_][1] * dir[1] + Ji[s_][2] * dir[2]);
+    };
+    if (a.fiber) {
+      double f[3] = {geo[9 * Q3 + k], geo[10 * Q3 + k], geo[11 * Q3 + k]};
+      const double fl = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+      for (int r = 0; r < 3; ++r) f[r] /= fl;
+      if (a.sheet) {
+        double sv[3] = {geo[12 * Q3 + k], geo[13 * Q3 + k], geo[14 * Q3 + k]};
+        const double d = sv[0] * f[0] + sv[1] * f[1] + sv[2] * f[2];
+        for (int r = 0; r < 3; ++r) sv[r] -= d * f[r];
+        const double sl = sqrt(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
+        for (int r = 0; r < 3; ++r) sv[r] /= sl;
+        const double nv[3] = {f[1] * sv[2] - f[2] * sv[1], f[2] * sv[0] - f[0] * sv[2],
+                              f[0] * sv[1] - f[1] * sv[0]};
+        put_v(f, 0);
+        put_v(sv, 3);
+        put_v(nv, 6);
+        continue;
+      }
+      put_v(f, 0);
+    }
+    // H[s][t] = W|J| sum_r Ji[s][r] Ji[t][r], symmetric (00 01 02 11 12 22)
+    const int is[6] = {0, 0, 0, 1, 1, 2}, it[6] = {0, 1, 2, 1, 2, 2};
+    for (int m = 0; m < 6; ++m)
+      geo[(3 + m) * Q3 + k] = wj * (Ji[is[m]][0] * Ji[it[m]][0] + Ji[is[m]][1] * Ji[it[m]][1] +
+                                    Ji[is[m]][2] * Ji[it[m]][2]);
+  }
+  // per member: reference gradients of u (slots 9..11) and w (12..14)
+  for (int bt = 0; bt < a.batch; ++bt) {
+    __syncthreads();
+    for (int i = tid; i < P3; i += SFT) fld[i] = a.u[(int64_t)bt * a.n_dof + a.ed[e * P3 + i]];
+    __syncthreads();
+    sf_grad(fld, sB, sD, P, Q, t1, t2, geo + 9 * Q3, geo + 10 * Q3, geo + 11 * Q3, nullptr);
+    for (int i = tid; i < P3; i += SFT) fld[i] = a.w[(int64_t)bt * a.n_dof + a.ed[e * P3 + i]];
+    __syncthreads();
+    sf_grad(fld, sB, sD, P, Q, t1, t2, geo + 12 * Q3, geo + 13 * Q3, geo + 14 * Q3, nullptr);
+    double gl = 0, gt = 0, gn = 0;
+    for (int k = tid; k < Q3; k += SFT) {
+      const double du[3] = {geo[9 * Q3 + k], geo[10 * Q3 + k], geo[11 * Q3 + k]};
+      const double dw[3] = {geo[12 * Q3 + k], geo[13 * Q3 + k], geo[14 * Q3 + k]};
+      auto dotv = [&](int slot, const double* d) {
+        return geo[slot * Q3 + k] * d[0] + geo[(slot + 1) * Q3 + k] * d[1] +
+               geo[(slot + 2) * Q3 + k] * d[2];
+      };
+      if (a.fiber && a.sheet) {
+        gl += dotv(0, du) * dotv(0, dw);
+        gt += dotv(3, du) * dotv(3, dw);
+        gn += dotv(6, du) * dotv(6, dw);
+        continue;
+      }
+      const double h00 = geo[3 * Q3 + k], h01 = geo[4 * Q3 + k], h02 = geo[5 * Q3 + k];
+      const double h11 = geo[6 * Q3 + k], h12 = geo[7 * Q3 + k], h22 = geo[8 * Q3 + k];
+      const double full = du[0] * (h00 * dw[0] + h01 * dw[1] + h02 * dw[2]) +
+                          du[1] * (h01 * dw[0] + h11 * dw[1] + h12 * dw[2]) +
+                          du[2] * (h02 * dw[0] + h12 * dw[1] + h22 * dw[2]);
+      if (a.fiber) {
+        const double fuw = dotv(0, du) * dotv(0, dw);
+        gl += fuw;
+        gt += full - fuw;
+      } else {
+        gt += full;
+      }
+    }
+    gl = block_sum(gl, sh);
+    gt = block_sum(gt, sh);
+    gn = block_sum(gn, sh);
+    if (tid == 0) {
+      double* out = a.g + ((int64_t)bt * a.n_elem + e) * 3;
+      out[0] = gl;
+      out[1] = gt;
+      out[2] = gn;
+    }
+  }
+}
+
 }  // namespace
 
 void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, double* g,
@@ -207,8 +428,14 @@ void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, dou
   a.u = u;
   a.w = w;
   a.g = g;
-  grad_kernel<<<dim3((unsigned)op.d.n_elem), GT, 0, s>>>(a);
-  MFSEM_LAUNCH("grad_kernel");
+  const size_t lds = sf_lds_doubles(a.P, a.Pm, a.Q) * sizeof(double);
+  if (lds <= SF_LDS_MAX) {
+    grad_sf_kernel<<<dim3((unsigned)op.d.n_elem), SFT, lds, s>>>(a);
+    MFSEM_LAUNCH("grad_sf_kernel");
+  } else {
+    grad_kernel<<<dim3((unsigned)op.d.n_elem), GT, 0, s>>>(a);
+    MFSEM_LAUNCH("grad_kernel");
+  }
 }
 
 }  // namespace mfsem
