@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MFSEM_ABI_VERSION 3
+#define MFSEM_ABI_VERSION 4
 #define MFSEM_MAX_P 8
 
 typedef enum {
@@ -360,6 +360,13 @@ mfsem_status mfsem_ap_bdf2_rhs(int64_t n, double dt, double chi, double cm,
                                double* w, double* w_old, const double* i_stim,
                                const double* mass_diag, double* b, double t, double v_act,
                                double* act, void* stream);
+
+/* out = 2 v - v_old: the linear extrapolation of a time series (the V* of
+ * the BDF2 scheme, Section 3), used as the initial guess of the next implicit
+ * solve in place of v.  [device] arrays of n FP64 values; out may be v or
+ * v_old (elementwise).                                                       */
+mfsem_status mfsem_extrapolate(int64_t n, const double* v, const double* v_old, double* out,
+                               void* stream);
 
 #ifdef __cplusplus
 }

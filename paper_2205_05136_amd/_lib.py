@@ -91,6 +91,7 @@ PROTOTYPES = {
     "mfsem_csr_nnz": (_ST, [_P, C.POINTER(C.c_int64)]),
     "mfsem_csr_assemble": (_ST, [_P, _P, _P, _P, _P]),
     "mfsem_csr_spmv": (_ST, [C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P]),
+    "mfsem_extrapolate": (_ST, [C.c_int64, _P, _P, _P, _P]),
     "mfsem_mg_workspace_bytes": (_ST, [C.POINTER(MgDesc), C.POINTER(C.c_size_t)]),
     "mfsem_mg_create": (_ST, [C.POINTER(MgDesc), _P, C.c_size_t, _P, C.POINTER(_P)]),
     "mfsem_mg_destroy": (_ST, [_P]),

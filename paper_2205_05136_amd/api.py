@@ -460,3 +460,11 @@ def ap_bdf2_rhs(V, V_old, w, w_old, mass_diag, dt, chi, cm, params: dict, i_stim
                                        _ptr(mass_diag), _ptr(b), float(t), float(v_act),
                                        _ptr(act), _stream()))
     return b
+
+
+def extrapolate(v, v_old, out=None):
+    """2 v - v_old, the initial guess of the next implicit solve (mfsem_extrapolate)."""
+    y = torch.empty_like(v) if out is None else out
+    _pointwise(v.numel(), v.device, v, v_old, y)
+    L.check(L.load().mfsem_extrapolate(v.numel(), _ptr(v), _ptr(v_old), _ptr(y), _stream()))
+    return y

@@ -32,6 +32,7 @@ void launch_ap_bdf2(int64_t n, double dt, double chi, double cm, const mfsem_ap_
                     const double* V, const double* Vo, double* w, double* wo, const double* istim,
                     const double* m, double* b, double t, double v_act, double* act,
                     hipStream_t s);
+void launch_extrapolate(int64_t n, const double* v, const double* vo, double* out, hipStream_t s);
 
 namespace {
 
@@ -567,6 +568,15 @@ mfsem_status mfsem_ap_bdf2_rhs(int64_t n, double dt, double chi, double cm,
     require(std::isfinite(t) && std::isfinite(v_act), "t and v_act must be finite");
     launch_ap_bdf2(n, dt, chi, cm, *prm, V, V_old, w, w_old, i_stim, mass_diag, b, t, v_act, act,
                    as_stream(stream));
+  });
+}
+
+mfsem_status mfsem_extrapolate(int64_t n, const double* v, const double* v_old, double* out,
+                               void* stream) {
+  return guarded([&] {
+    require(n >= 0, "n must be >= 0");
+    require(n == 0 || (v && v_old && out), "NULL array");
+    launch_extrapolate(n, v, v_old, out, as_stream(stream));
   });
 }
 

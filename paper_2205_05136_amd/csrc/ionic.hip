@@ -73,7 +73,21 @@ __global__ void ap_bdf2_kernel(int64_t n, double dt, double chi, double cm, mfse
   }
 }
 
+__global__ void extrapolate_kernel(int64_t n, const double* v, const double* vo, double* out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = 2.0 * v[i] - vo[i];
+}
+
 }  // namespace
+
+void launch_extrapolate(int64_t n, const double* v, const double* vo, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  extrapolate_kernel<<<(unsigned)blocks, 256, 0, s>>>(n, v, vo, out);
+  MFSEM_LAUNCH("extrapolate_kernel");
+}
 
 void launch_ap_bdf2(int64_t n, double dt, double chi, double cm, const mfsem_ap_params& prm,
                     const double* V, const double* Vo, double* w, double* wo, const double* istim,

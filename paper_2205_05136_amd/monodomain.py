@@ -1,7 +1,9 @@
 """Full monodomain time loop: the outer loop of Alg. 1 around the hot path.
 
 Two schemes, both a pointwise ionic update and SEM-NI right-hand side followed
-by one GMG-PCG solve warm-started from V^n (Section 5):
+by one GMG-PCG solve, warm-started (Section 5) from the extrapolation
+2 V^n - V^{n-1} (guess="extrapolate", about a quarter fewer iterations) or
+from V^n (guess="previous"):
   "imex1": first-order IMEX (mfsem_ap_imex_rhs), (alpha M + K) V^{n+1} = b with
            alpha = chi Cm / dt;
   "bdf2":  the paper's partitioned BDF2 scheme (Section 3) with the
@@ -40,9 +42,14 @@ class StepStats:
 class Monodomain:
     def __init__(self, spec, dt, chi, cm, ap_params: dict, stimulus: Stimulus,
                  coarsening=(("p", 2), ("p", 1)), degree=3, precision=torch.float32,
-                 rtol=1e-10, atol=0.0, device="cuda", scheme="imex1", v_act=-40.0):
+                 rtol=1e-10, atol=0.0, device="cuda", scheme="imex1", v_act=-40.0,
+                 guess="extrapolate"):
         if scheme not in ("imex1", "bdf2"):
             raise ValueError("scheme must be 'imex1' or 'bdf2'")
+        if guess not in ("extrapolate", "previous"):
+            raise ValueError("guess must be 'extrapolate' or 'previous'")
+        # initial guess of each solve: 2 V^n - V^{n-1} (the scheme's V*), or V^n
+        self.guess = guess
         self.scheme, self.v_act = scheme, float(v_act)
         scale = 1.5 if scheme == "bdf2" else 1.0
         self.spec = spec.with_(alpha=scale * chi * cm / dt)
@@ -85,7 +92,8 @@ class Monodomain:
                             self.cm, self.prm, i_stim=stim, out=self.b, t=self.t,
                             v_act=self.v_act, act=self.act)
         ev[1].record()
-        V, info = api.pcg(self.op, self.b, x0=self.V, mg=self.mg, rtol=self.rtol, atol=self.atol,
+        x0 = api.extrapolate(self.V, self.V_old) if self.guess == "extrapolate" else self.V
+        V, info = api.pcg(self.op, self.b, x0=x0, mg=self.mg, rtol=self.rtol, atol=self.atol,
                           max_it=500)
         ev[2].record()
         self.V_old = self.V

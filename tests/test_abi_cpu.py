@@ -121,4 +121,7 @@ def test_null_handles_are_rejected_without_a_device():
     nnz = C.c_int64()
     assert lib.mfsem_csr_nnz(None, C.byref(nnz)) == -1
     assert lib.mfsem_csr_spmv(-1, 0, None, None, None, None, None, None) == -1
+    assert lib.mfsem_extrapolate(-1, None, None, None, None) == -1
+    assert lib.mfsem_extrapolate(5, None, None, None, None) == -1
+    assert lib.mfsem_extrapolate(0, None, None, None, None) == 0
     assert lib.mfsem_csr_spmv(4, -1, None, None, None, None, None, None) == -1

@@ -201,3 +201,23 @@ def test_full_size_sampled_rows(name):
     got = to_np(y[torch.as_tensor(rows, device="cuda")])
     scale = np.abs(ref).max()
     assert np.max(np.abs(got - ref)) <= 1e-12 * scale, (got - ref)
+
+
+def test_extrapolated_guess_gives_the_same_steps():
+    """The initial guess 2 V^n - V^{n-1} (mfsem_extrapolate, exact elementwise)
+    changes only the iterations of each solve, not the time steps."""
+    announce("extrapolated initial guess")
+    v = synth.uniform(60, 1000)
+    vo = synth.uniform(61, 1000)
+    out = to_np(mf.extrapolate(to_dev(v), to_dev(vo)))
+    assert np.array_equal(out, 2.0 * v - vo)
+    spec = synth.slab(3, (6, 3, 2)).with_(length=(3.0, 1.5, 1.0))
+    stim = md.Stimulus(lo=(0, 0, 0), hi=(1.0, 1.0, 1.0), amplitude=50.0, duration=1.0)
+    runs = {}
+    for guess in ("extrapolate", "previous"):
+        sim = md.Monodomain(spec, 0.05, synth.CHI, synth.CM, synth.AP_PARAMS, stim,
+                            precision=torch.float64, rtol=1e-13, scheme="bdf2", guess=guess)
+        its = [sim.step().iters[0] for _ in range(30)]
+        runs[guess] = (to_np(sim.V), sum(its))
+    assert rel_l2(runs["extrapolate"][0], runs["previous"][0]) <= 1e-10
+    assert runs["extrapolate"][1] < runs["previous"][1], runs
