@@ -189,6 +189,22 @@ def test_apply_f32(p, quad, q):
     assert rel_l2(d, A.diagonal()) <= TOL32
 
 
+@pytest.mark.parametrize("quad,q", [("gll", 0), ("gauss", 5)])
+def test_apply_singular_sigma(quad, q):
+    """sigma_t = 0 makes sigma = sigma_l f f^T singular: det G = 0, so the mass
+    weight cannot be recovered from it and the kernels read the stored W|J|."""
+    announce(f"apply singular sigma {quad}")
+    spec = _spec(3, (5, 3, 2), quad=quad, nq1d=q).with_(sigma=(0.17, 0.0, 0.0))
+    prob, A, M, K = oracle_problem(spec)
+    x = synth.uniform(106, spec.n_dof)
+    kws = (dict(), dict(structured=False)) if quad == "gll" else (dict(),)
+    for kw in kws:
+        op, _ = _op(spec, store_f32=True, **kw)
+        assert rel_l2(to_np(op.apply(to_dev(x))), A @ x) <= TOL64, kw
+        assert rel_l2(to_np(op.apply(to_dev(x, torch.float32))), A @ x) <= TOL32, kw
+        assert rel_l2(to_np(op.apply_mass(to_dev(x))), M @ x) <= TOL64, kw
+
+
 def test_apply_batch_sigma():
     announce("apply batch of 3 sigma sets")
     spec = _spec(3, (4, 3, 2))
