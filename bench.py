@@ -6,7 +6,7 @@ alpha = chi*Cm/dt = 28 (229,425 DOFs); FP64 apply and GMG-PCG with
 p-coarsening 4 -> 2 -> 1 and Chebyshev degree 3, random right-hand side.
 
 One timed step = one pass of the hot path on that input:
-  * R back-to-back operator applies y = A x (FP64; --apply-reps, default 20),
+  * R back-to-back operator applies y = A x (FP64; --apply-reps, default 100),
     then R launches of the kernel alone (y += A x) in FP64 and in FP32,
   * one FP64 GMG-PCG solve A u = f to ||r||/||f|| <= 1e-10 from u0 = 0,
   * one mixed-precision solve (FP32 V-cycle inside FP64 flexible CG), same tolerance.
@@ -321,7 +321,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pcg", action="store_true")
-    ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--apply-reps", type=int, default=100)
     ap.add_argument("--coarsening", default=None,
                     help="multigrid chain below the finest level, e.g. p5,p3,p1 or p2,p1,h "
                          "(default: the workload's)")

@@ -14,9 +14,19 @@ import torch
 from . import _lib as L
 
 
-def _stream(stream=None):
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return C.c_void_p(s.cuda_stream)
+# torch's current stream as a raw handle, without building a Stream object
+# (that costs about 3 us per call, as much as a kernel launch)
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+def _stream(stream=None, device=None):
+    """The HIP stream to enqueue on: `stream`, else torch's current stream of
+    device index `device` (default: the current device)."""
+    if stream is not None:
+        return C.c_void_p(stream.cuda_stream)
+    if _raw_stream is not None:
+        return C.c_void_p(_raw_stream(torch.cuda.current_device() if device is None else device))
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def _ptr(t):
@@ -133,6 +143,8 @@ class Operator:
         self.handle = h
         self.alpha = alpha
         self.store_f64, self.store_f32 = store_f64, store_f32
+        self._lib = lib
+        self._dev = self.ws.device.index
 
     @classmethod
     def from_spec(cls, spec, box=None, device="cuda", **kw):
@@ -168,14 +180,15 @@ class Operator:
         """y = A x (mfsem_op_apply)."""
         x = self._vec(x)
         y = torch.empty_like(x) if out is None else self._vec(out)
-        L.check(L.load().mfsem_op_apply(self.handle, self._dt(x), _ptr(x), _ptr(y), _stream(stream)))
+        L.check(self._lib.mfsem_op_apply(self.handle, self._dt(x), x.data_ptr(), y.data_ptr(),
+                                         _stream(stream, self._dev)))
         return y
 
     def apply_add(self, x, y, stream=None):
         """y += A x (mfsem_op_apply_add), one kernel launch."""
         x, y = self._vec(x), self._vec(y)
-        L.check(L.load().mfsem_op_apply_add(self.handle, self._dt(x), _ptr(x), _ptr(y),
-                                            _stream(stream)))
+        L.check(self._lib.mfsem_op_apply_add(self.handle, self._dt(x), x.data_ptr(), y.data_ptr(),
+                                             _stream(stream, self._dev)))
         return y
 
     def apply_mass(self, x, out=None):

@@ -53,6 +53,10 @@ mfsem_status guarded(F&& f) {
 void require(bool ok, const std::string& msg) {
   if (!ok) fail(MFSEM_EINVAL, msg);
 }
+// literal messages build no std::string unless the check fails
+void require(bool ok, const char* msg) {
+  if (!ok) fail(MFSEM_EINVAL, msg);
+}
 
 void require_aligned(const void* p, size_t a, const char* what) {
   require((reinterpret_cast<uintptr_t>(p) % a) == 0,
