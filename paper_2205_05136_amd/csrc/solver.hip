@@ -79,14 +79,14 @@ void estimate_lambda(mfsem_mg& mg, mfsem_mg_level& L, int level, double* scratch
   for (int b = 0; b < B; ++b) { hc[2 * b] = 0.0; hc[2 * b + 1] = 1.0; }
   MFSEM_HIP(hipMemcpy(cdev, hc.data(), 2 * B * sizeof(double), hipMemcpyHostToDevice));
   vlin<T>(p, z, n, B, cdev, s);
-  vdot2<T>(r, z, nullptr, n, B, partial, red, s);
+  vdot2<T, T>(r, z, nullptr, n, B, partial, red, s);
   MFSEM_HIP(hipMemcpyAsync(hred.data(), red, 2 * B * sizeof(double), hipMemcpyDeviceToHost, s));
   MFSEM_HIP(hipStreamSynchronize(s));
   for (int b = 0; b < B; ++b) rz[b] = hred[2 * b];
   std::vector<int> live(B, 1);
   for (int it = 0; it < mg.d.eig_iters; ++it) {
     launch_apply<T>(*L.op, p, q, L.op->alpha, true, s);
-    vdot2<T>(p, q, nullptr, n, B, partial, red, s);
+    vdot2<T, T>(p, q, nullptr, n, B, partial, red, s);
     MFSEM_HIP(hipMemcpyAsync(hred.data(), red, 2 * B * sizeof(double), hipMemcpyDeviceToHost, s));
     MFSEM_HIP(hipStreamSynchronize(s));
     for (int b = 0; b < B; ++b) {
@@ -99,7 +99,7 @@ void estimate_lambda(mfsem_mg& mg, mfsem_mg_level& L, int level, double* scratch
     MFSEM_HIP(hipMemcpy(cdev, hc.data(), 2 * B * sizeof(double), hipMemcpyHostToDevice));
     vlin<T>(r, q, n, B, cdev, s);
     vmul<T>(z, dinv, r, n, B, s);
-    vdot2<T>(r, z, nullptr, n, B, partial, red, s);
+    vdot2<T, T>(r, z, nullptr, n, B, partial, red, s);
     MFSEM_HIP(hipMemcpyAsync(hred.data(), red, 2 * B * sizeof(double), hipMemcpyDeviceToHost, s));
     MFSEM_HIP(hipStreamSynchronize(s));
     for (int b = 0; b < B; ++b) {
@@ -484,15 +484,19 @@ mfsem_status pcg_solve(const mfsem_op& op, const mfsem_mg* mg, const double* b, 
   MFSEM_HIP(hipStreamSynchronize(s));
   MFSEM_HIP(hipMemcpy(w.sc, hs.data(), B * sizeof(PcgScalars), hipMemcpyHostToDevice));
 
+  // With the FP32 V-cycle, r32 = (float)r is written by the kernels that
+  // update r, and z stays in FP32: every read of z converts it exactly, so the
+  // iteration equals the one with an FP64 copy of z, without the two casts.
+  // z_old (flexible) is then kept as FP32 in the z_old buffer.
+  const bool mixed = mg && mg->prec == MFSEM_F32;
+  float* zo32 = reinterpret_cast<float*>(w.zo);
   auto precondition = [&]() {
     if (!mg) {
       MFSEM_HIP(hipMemcpyAsync(w.z, w.r, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
-    } else if (mg->prec == MFSEM_F64) {
+    } else if (!mixed) {
       mg_vcycle(*mg, w.r, w.z, s);
     } else {
-      vcast<double, float>(w.r, w.r32, (int64_t)nb, s);
       mg_vcycle(*mg, w.r32, w.z32, s);
-      vcast<float, double>(w.z32, w.z, (int64_t)nb, s);
     }
   };
   auto fetch = [&]() {
@@ -503,7 +507,7 @@ mfsem_status pcg_solve(const mfsem_op& op, const mfsem_mg* mg, const double* b, 
   // r = b - A x; q is left at zero, and every later q = A p adds into it
   // (the update of x and r clears it again)
   launch_apply<double>(op, x, w.q, op.alpha, true, s);
-  vresidual(b, w.q, w.r, n, B, w.partial, w.red, true, w.sc, s);
+  vresidual(b, w.q, w.r, mixed ? w.r32 : nullptr, n, B, w.partial, w.red, true, w.sc, s);
   fetch();
   std::vector<double> tol(B);
   std::vector<char> done(B, 0);
@@ -527,14 +531,23 @@ mfsem_status pcg_solve(const mfsem_op& op, const mfsem_mg* mg, const double* b, 
 
   for (int it = 1; live > 0 && it <= o.max_it; ++it) {
     precondition();
-    vdot2<double>(w.r, w.z, o.flexible ? w.zo : nullptr, n, B, w.partial, w.red, s, w.sc,
-                  it == 1 ? PCG_SET_RZ_FIRST : PCG_SET_RZ);
-    if (o.flexible)
-      MFSEM_HIP(hipMemcpyAsync(w.zo, w.z, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
-    vp(w.p, w.z, n, B, w.sc, s);
+    const int rz_what = it == 1 ? PCG_SET_RZ_FIRST : PCG_SET_RZ;
+    if (mixed) {
+      vdot2<double, float>(w.r, w.z32, o.flexible ? zo32 : nullptr, n, B, w.partial, w.red, s,
+                           w.sc, rz_what);
+      if (o.flexible)
+        MFSEM_HIP(hipMemcpyAsync(zo32, w.z32, nb * sizeof(float), hipMemcpyDeviceToDevice, s));
+      vp<float>(w.p, w.z32, n, B, w.sc, s);
+    } else {
+      vdot2<double, double>(w.r, w.z, o.flexible ? w.zo : nullptr, n, B, w.partial, w.red, s,
+                            w.sc, rz_what);
+      if (o.flexible)
+        MFSEM_HIP(hipMemcpyAsync(w.zo, w.z, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+      vp<double>(w.p, w.z, n, B, w.sc, s);
+    }
     launch_apply<double>(op, w.p, w.q, op.alpha, true, s, true);
-    vdot2<double>(w.p, w.q, nullptr, n, B, w.partial, w.red, s, w.sc, PCG_SET_PQ);
-    vxr(x, w.r, w.p, w.q, n, B, w.sc, w.partial, w.red, s);
+    vdot2<double, double>(w.p, w.q, nullptr, n, B, w.partial, w.red, s, w.sc, PCG_SET_PQ);
+    vxr(x, w.r, mixed ? w.r32 : nullptr, w.p, w.q, n, B, w.sc, w.partial, w.red, s);
     fetch();
     changed = false;
     live = 0;

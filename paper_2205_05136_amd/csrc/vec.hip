@@ -40,9 +40,11 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 // partial[(bt*nblk + blk)*2 + {0,1}] = sum over the block's chunk of a*b and a*c
-template <typename T>
-__global__ __launch_bounds__(VT) void dot2_kernel(const T* __restrict__ a, const T* __restrict__ b,
-                                                  const T* __restrict__ c, int64_t n,
+// (products and sums in FP64 whatever the storage types)
+template <typename TA, typename TB>
+__global__ __launch_bounds__(VT) void dot2_kernel(const TA* __restrict__ a,
+                                                  const TB* __restrict__ b,
+                                                  const TB* __restrict__ c, int64_t n,
                                                   double* __restrict__ partial) {
   __shared__ double sh[VT / 64];
   const int bt = blockIdx.y;
@@ -120,10 +122,12 @@ __global__ __launch_bounds__(VT) void reduce_kernel(const double* __restrict__ p
   if (sc && threadIdx.x == 0) pcg_update(sc[bt], v[0], v[1], what);
 }
 
-// r = b - q ; partial sums of r.r and b.b; q is cleared after use (zero_q)
+// r = b - q ; partial sums of r.r and b.b; q is cleared after use (zero_q);
+// r32 (may be null) receives r rounded to FP32
 __global__ __launch_bounds__(VT) void residual_kernel(const double* __restrict__ b,
                                                       double* __restrict__ q,
-                                                      double* __restrict__ r, int64_t n,
+                                                      double* __restrict__ r,
+                                                      float* __restrict__ r32, int64_t n,
                                                       double* __restrict__ partial, int zero_q) {
   __shared__ double sh[VT / 64];
   const int bt = blockIdx.y;
@@ -134,6 +138,7 @@ __global__ __launch_bounds__(VT) void residual_kernel(const double* __restrict__
     const double rv = q ? bv - q[off + i] : bv;
     if (q && zero_q) q[off + i] = 0.0;
     r[off + i] = rv;
+    if (r32) r32[off + i] = (float)rv;
     s0 += rv * rv;
     s1 += bv * bv;
   }
@@ -147,8 +152,10 @@ __global__ __launch_bounds__(VT) void residual_kernel(const double* __restrict__
 }
 
 // alpha = rz/pq; x += alpha p ; r -= alpha q ; partial r.r (finished members
-// are left as they are); q is cleared for the next q = A p, which accumulates
+// are left as they are); q is cleared for the next q = A p, which accumulates;
+// r32 (may be null) receives the new r rounded to FP32
 __global__ __launch_bounds__(VT) void xr_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                float* __restrict__ r32,
                                                 const double* __restrict__ p,
                                                 double* __restrict__ q, int64_t n,
                                                 const PcgScalars* __restrict__ sc,
@@ -164,6 +171,7 @@ __global__ __launch_bounds__(VT) void xr_kernel(double* __restrict__ x, double* 
       x[off + i] += al * p[off + i];
       const double rv = r[off + i] - al * q[off + i];
       r[off + i] = rv;
+      if (r32) r32[off + i] = (float)rv;
       s0 += rv * rv;
     }
     q[off + i] = 0.0;
@@ -177,14 +185,15 @@ __global__ __launch_bounds__(VT) void xr_kernel(double* __restrict__ x, double* 
 }
 
 // p = z + beta p (beta = 0 on the first iteration via sc.beta)
-__global__ __launch_bounds__(VT) void p_kernel(double* __restrict__ p, const double* __restrict__ z,
+template <typename TZ>
+__global__ __launch_bounds__(VT) void p_kernel(double* __restrict__ p, const TZ* __restrict__ z,
                                                int64_t n, const PcgScalars* __restrict__ sc) {
   const int bt = blockIdx.y;
   const int64_t off = (int64_t)bt * n;
   if (!sc[bt].active) return;
   const double be = sc[bt].beta;
   for (int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
-    p[off + i] = (be != 0.0) ? z[off + i] + be * p[off + i] : z[off + i];
+    p[off + i] = (be != 0.0) ? (double)z[off + i] + be * p[off + i] : (double)z[off + i];
 }
 
 // Chebyshev step: d = c1*d + c2*dinv*(b - t); x = (overwrite ? d : x + d).
@@ -281,36 +290,37 @@ void vcast(const A* x, B* y, int64_t n, hipStream_t s) {
   MFSEM_LAUNCH("cast_kernel");
 }
 
-template <typename T>
-void vdot2(const T* a, const T* b, const T* c, int64_t n, int batch, double* partial,
+template <typename TA, typename TB>
+void vdot2(const TA* a, const TB* b, const TB* c, int64_t n, int batch, double* partial,
            double* out, hipStream_t s, PcgScalars* sc, int what) {
   const unsigned nb = grid_for(n);
-  dot2_kernel<T><<<dim3(nb, batch), VT, 0, s>>>(a, b, c, n, partial);
+  dot2_kernel<TA, TB><<<dim3(nb, batch), VT, 0, s>>>(a, b, c, n, partial);
   MFSEM_LAUNCH("dot2_kernel");
   reduce_kernel<<<batch, VT, 0, s>>>(partial, (int)nb, out, sc, what);
   MFSEM_LAUNCH("reduce_kernel");
 }
 
-void vresidual(const double* b, double* q, double* r, int64_t n, int batch, double* partial,
-               double* out, bool zero_q, PcgScalars* sc, hipStream_t s) {
+void vresidual(const double* b, double* q, double* r, float* r32, int64_t n, int batch,
+               double* partial, double* out, bool zero_q, PcgScalars* sc, hipStream_t s) {
   const unsigned nb = grid_for(n);
-  residual_kernel<<<dim3(nb, batch), VT, 0, s>>>(b, q, r, n, partial, zero_q ? 1 : 0);
+  residual_kernel<<<dim3(nb, batch), VT, 0, s>>>(b, q, r, r32, n, partial, zero_q ? 1 : 0);
   MFSEM_LAUNCH("residual_kernel");
   reduce_kernel<<<batch, VT, 0, s>>>(partial, (int)nb, out, sc, PCG_SET_RR_BB);
   MFSEM_LAUNCH("reduce_kernel");
 }
 
-void vxr(double* x, double* r, const double* p, double* q, int64_t n, int batch,
+void vxr(double* x, double* r, float* r32, const double* p, double* q, int64_t n, int batch,
          PcgScalars* sc, double* partial, double* out, hipStream_t s) {
   const unsigned nb = grid_for(n);
-  xr_kernel<<<dim3(nb, batch), VT, 0, s>>>(x, r, p, q, n, sc, partial);
+  xr_kernel<<<dim3(nb, batch), VT, 0, s>>>(x, r, r32, p, q, n, sc, partial);
   MFSEM_LAUNCH("xr_kernel");
   reduce_kernel<<<batch, VT, 0, s>>>(partial, (int)nb, out, sc, PCG_SET_RR);
   MFSEM_LAUNCH("reduce_kernel");
 }
 
-void vp(double* p, const double* z, int64_t n, int batch, const PcgScalars* sc, hipStream_t s) {
-  p_kernel<<<dim3(grid_for(n), batch), VT, 0, s>>>(p, z, n, sc);
+template <typename TZ>
+void vp(double* p, const TZ* z, int64_t n, int batch, const PcgScalars* sc, hipStream_t s) {
+  p_kernel<TZ><<<dim3(grid_for(n), batch), VT, 0, s>>>(p, z, n, sc);
   MFSEM_LAUNCH("p_kernel");
 }
 
@@ -356,8 +366,9 @@ void vrandom(double* x, int64_t n, uint64_t seed, hipStream_t s) {
 
 #define MFSEM_INST(T)                                                                        \
   template void vfill<T>(T*, int64_t, T, hipStream_t);                                       \
-  template void vdot2<T>(const T*, const T*, const T*, int64_t, int, double*, double*,       \
-                         hipStream_t, PcgScalars*, int);                                     \
+  template void vdot2<T, T>(const T*, const T*, const T*, int64_t, int, double*, double*,    \
+                            hipStream_t, PcgScalars*, int);                                  \
+  template void vp<T>(double*, const T*, int64_t, int, const PcgScalars*, hipStream_t);      \
   template void vcheb<T>(T*, T*, T*, T*, const T*, int64_t, int, const double*, bool, bool,  \
                          bool, hipStream_t);                                                 \
   template void vaxpy<T>(T*, T*, int64_t, bool, hipStream_t);                                \
@@ -371,5 +382,7 @@ template void vfill<unsigned long long>(unsigned long long*, int64_t, unsigned l
                                         hipStream_t);
 template void vcast<double, float>(const double*, float*, int64_t, hipStream_t);
 template void vcast<float, double>(const float*, double*, int64_t, hipStream_t);
+template void vdot2<double, float>(const double*, const float*, const float*, int64_t, int,
+                                   double*, double*, hipStream_t, PcgScalars*, int);
 
 }  // namespace mfsem

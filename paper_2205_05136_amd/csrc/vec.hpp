@@ -15,21 +15,22 @@ enum { PCG_SET_RR_BB = 0, PCG_SET_PQ = 1, PCG_SET_RR = 2, PCG_SET_RZ_FIRST = 3, 
 
 int dot_blocks(int64_t n);  // partial-sum blocks per member for vectors of length n
 
-// out[bt*2 + {0,1}] = (a.b, a.c) per member (c may be null -> 0); with sc,
-// the reduction also applies the scalar update `what` to each member
-template <typename T>
-void vdot2(const T* a, const T* b, const T* c, int64_t n, int batch, double* partial,
+// out[bt*2 + {0,1}] = (a.b, a.c) per member (c may be null -> 0), in FP64; with
+// sc, the reduction also applies the scalar update `what` to each member
+template <typename TA, typename TB>
+void vdot2(const TA* a, const TB* b, const TB* c, int64_t n, int batch, double* partial,
            double* out, hipStream_t s, PcgScalars* sc = nullptr, int what = 0);
 // r = b - q (q may be null; cleared afterwards when zero_q), out = (r.r, b.b),
-// then sc[bt].{rr, bb} = out when sc is given
-void vresidual(const double* b, double* q, double* r, int64_t n, int batch, double* partial,
-               double* out, bool zero_q, PcgScalars* sc, hipStream_t s);
+// then sc[bt].{rr, bb} = out when sc is given; r32 (may be null) = (float)r
+void vresidual(const double* b, double* q, double* r, float* r32, int64_t n, int batch,
+               double* partial, double* out, bool zero_q, PcgScalars* sc, hipStream_t s);
 // x += alpha p, r -= alpha q with alpha from sc; q = 0; out[bt*2] = r.r and
-// sc[bt].rr is updated for active members
-void vxr(double* x, double* r, const double* p, double* q, int64_t n, int batch,
+// sc[bt].rr is updated for active members; r32 (may be null) = (float)r
+void vxr(double* x, double* r, float* r32, const double* p, double* q, int64_t n, int batch,
          PcgScalars* sc, double* partial, double* out, hipStream_t s);
-// p = z + beta p (p = z when beta == 0)
-void vp(double* p, const double* z, int64_t n, int batch, const PcgScalars* sc, hipStream_t s);
+// p = z + beta p (p = z when beta == 0); z in FP64 or FP32
+template <typename TZ>
+void vp(double* p, const TZ* z, int64_t n, int batch, const PcgScalars* sc, hipStream_t s);
 // d = c1 d + c2 dinv (b - t); x = overwrite ? d : x + d   (coef [batch][2]);
 // clear_t / clear_b set t / b to zero after they are read
 template <typename T>
