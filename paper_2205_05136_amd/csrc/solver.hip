@@ -445,7 +445,7 @@ PcgWs pcg_layout(const mfsem_op& op, const mfsem_mg* mg, bool flexible, Arena& a
   w.z = a.take_n<double>(nb);
   w.p = a.take_n<double>(nb);
   w.q = a.take_n<double>(nb);
-  w.zo = a.take_n<double>(nb);  // used by the flexible variant
+  w.zo = a.take_n<double>(nb);  // the flexible variant's second z buffer
   (void)flexible;
   if (mg && mg->prec == MFSEM_F32) {
     w.r32 = a.take_n<float>(nb);
@@ -487,16 +487,18 @@ mfsem_status pcg_solve(const mfsem_op& op, const mfsem_mg* mg, const double* b, 
   // With the FP32 V-cycle, r32 = (float)r is written by the kernels that
   // update r, and z stays in FP32: every read of z converts it exactly, so the
   // iteration equals the one with an FP64 copy of z, without the two casts.
-  // z_old (flexible) is then kept as FP32 in the z_old buffer.
+  // The flexible variant keeps the previous z by alternating two z buffers
+  // (the z_old buffer holds FP32 values in the mixed case).
   const bool mixed = mg && mg->prec == MFSEM_F32;
-  float* zo32 = reinterpret_cast<float*>(w.zo);
-  auto precondition = [&]() {
+  double* z64[2] = {w.z, w.zo};
+  float* z32[2] = {w.z32, reinterpret_cast<float*>(w.zo)};
+  auto precondition = [&](int cur) {
     if (!mg) {
-      MFSEM_HIP(hipMemcpyAsync(w.z, w.r, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+      MFSEM_HIP(hipMemcpyAsync(z64[cur], w.r, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else if (!mixed) {
-      mg_vcycle(*mg, w.r, w.z, s);
+      mg_vcycle(*mg, w.r, z64[cur], s);
     } else {
-      mg_vcycle(*mg, w.r32, w.z32, s);
+      mg_vcycle(*mg, w.r32, z32[cur], s);
     }
   };
   auto fetch = [&]() {
@@ -530,20 +532,19 @@ mfsem_status pcg_solve(const mfsem_op& op, const mfsem_mg* mg, const double* b, 
   if (changed) MFSEM_HIP(hipMemcpy(w.sc, hs.data(), B * sizeof(PcgScalars), hipMemcpyHostToDevice));
 
   for (int it = 1; live > 0 && it <= o.max_it; ++it) {
-    precondition();
+    // z of this iteration, and the previous one for the flexible beta
+    const int cur = o.flexible ? (it & 1) : 0;
+    const bool use_old = o.flexible && it > 1;
+    precondition(cur);
     const int rz_what = it == 1 ? PCG_SET_RZ_FIRST : PCG_SET_RZ;
     if (mixed) {
-      vdot2<double, float>(w.r, w.z32, o.flexible ? zo32 : nullptr, n, B, w.partial, w.red, s,
-                           w.sc, rz_what);
-      if (o.flexible)
-        MFSEM_HIP(hipMemcpyAsync(zo32, w.z32, nb * sizeof(float), hipMemcpyDeviceToDevice, s));
-      vp<float>(w.p, w.z32, n, B, w.sc, s);
+      vdot2<double, float>(w.r, z32[cur], use_old ? z32[cur ^ 1] : nullptr, n, B, w.partial,
+                           w.red, s, w.sc, rz_what);
+      vp<float>(w.p, z32[cur], n, B, w.sc, s);
     } else {
-      vdot2<double, double>(w.r, w.z, o.flexible ? w.zo : nullptr, n, B, w.partial, w.red, s,
-                            w.sc, rz_what);
-      if (o.flexible)
-        MFSEM_HIP(hipMemcpyAsync(w.zo, w.z, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
-      vp<double>(w.p, w.z, n, B, w.sc, s);
+      vdot2<double, double>(w.r, z64[cur], use_old ? z64[cur ^ 1] : nullptr, n, B, w.partial,
+                            w.red, s, w.sc, rz_what);
+      vp<double>(w.p, z64[cur], n, B, w.sc, s);
     }
     launch_apply<double>(op, w.p, w.q, op.alpha, true, s, true);
     vdot2<double, double>(w.p, w.q, nullptr, n, B, w.partial, w.red, s, w.sc, PCG_SET_PQ);
