@@ -446,6 +446,32 @@ def test_mixed_precision_pcg():
     assert rel_l2(to_np(x2), x_ref) <= TOL64
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("flexible", [False, True])
+def test_pcg_variants(precision, flexible):
+    """Standard and flexible CG around the FP64 and the FP32 V-cycle (and the
+    unpreconditioned loop in both forms): every combination reaches the direct
+    solution, and the preconditioned ones in a few dozen iterations."""
+    announce(f"pcg {precision} flexible={flexible}")
+    spec, chain = CHAINS["p4-2-1"]
+    A = oracle_problem(spec)[1]
+    f = synth.uniform(7, spec.n_dof)
+    x_ref = spla.spsolve(A.tocsc(), f)
+    dt = torch.float64 if precision == "f64" else torch.float32
+    ops, mg = mf.hierarchy(spec, coarsening=chain, degree=3, precision=dt)
+    # standard CG assumes a symmetric preconditioner, which the FP32 V-cycle is
+    # only to single precision: it is held to the mixed-precision bar
+    rtol, bar = (1e-10, 1e-8) if (precision == "f32" and not flexible) else (1e-13, 1e-11)
+    x, info = mf.pcg(ops[0], to_dev(f), mg=mg, rtol=rtol, max_it=300, flexible=flexible)
+    assert info.status == [0], info.status
+    assert info.iters[0] <= 60, info.iters
+    assert rel_l2(to_np(x), x_ref) <= bar
+    if precision == "f64":
+        x0, info0 = mf.pcg(ops[0], to_dev(f), rtol=1e-13, max_it=5000, flexible=flexible)
+        assert info0.status == [0]
+        assert rel_l2(to_np(x0), x_ref) <= 1e-11
+
+
 def test_batched_pcg_and_grad():
     announce("batched pcg + grad")
     spec = synth.BoxSpec(p=3, n=(3, 3, 2), length=(1.5, 1.5, 1.0), fiber=True,
