@@ -244,8 +244,11 @@ mfsem_status mfsem_csr_spmv(int64_t n_rows, int64_t nnz, const int64_t* row_ptr,
  * is Chebyshev-Jacobi of `degree` on [lo_frac, hi_frac] * lambda_max, with
  * lambda_max from `eig_iters` Jacobi-CG steps on a seeded start vector
  * (Section 5: 10 steps, [0.08, 1.2]); the coarsest level is a Chebyshev
- * smoothing of `coarse_degree` from zero.  The cycle is symmetric, so it is a
- * valid CG preconditioner.  Every level must hold geometry in `precision`.  */
+ * smoothing of `coarse_degree` from zero.  The polynomial is applied in its
+ * factored form, `degree` damped-Jacobi steps weighted by the inverse roots
+ * (largest root first), which ends on the same iterate as the three-term
+ * recurrence.  The cycle is symmetric, so it is a valid CG preconditioner.
+ * Every level must hold geometry in `precision`.                            */
 typedef struct {
   int32_t kind;             /* mfsem_transfer_kind */
   const int32_t* parent;    /* H: [device] [n_elem_fine], coarse element of each fine

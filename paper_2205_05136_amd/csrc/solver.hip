@@ -1,13 +1,17 @@
 // Geometric multigrid V-cycle with Chebyshev-Jacobi smoothing, and the (P)CG
 // driver (Sections 4 and 4.3; smoother parameters from Section 5).
 //
-// Chebyshev smoothing of A x = b on [lo, hi] * lambda_max, with
-// theta = (l_hi + l_lo)/2, delta = (l_hi - l_lo)/2, s = theta/delta, rho_1 = 1/s:
-//   step 1:  d = D^{-1} (b - A x0) / theta,            x = x0 + d
-//   step j:  rho_j = 1/(2s - rho_{j-1}),
-//            d = rho_j rho_{j-1} d + (2 rho_j/delta) D^{-1}(b - A x),  x += d
-// From x0 = 0 the first product with A is skipped.  lambda_max per level
-// comes from the Lanczos tridiagonal of a few Jacobi-preconditioned CG steps.
+// Chebyshev smoothing of A x = b on [lo, hi] * lambda_max: k steps reduce the
+// error by the degree-k Chebyshev polynomial of D^{-1} A scaled to 1 at zero.
+// The three-term recurrence (theta = (l_hi + l_lo)/2, delta = (l_hi - l_lo)/2,
+// s = theta/delta, rho_1 = 1/s; d = D^{-1}(b - A x0)/theta, then
+// rho_j = 1/(2s - rho_{j-1}), d = rho_j rho_{j-1} d + (2 rho_j/delta) D^{-1}(b - A x),
+// x += d) is applied here in its factored form: the same polynomial as k
+// damped-Jacobi steps with weights 1/r over its roots r (cheb_coefficients),
+// which gives the same iterate after the k steps with one vector less to read
+// and write per step.  From x0 = 0 the first product with A is skipped.
+// lambda_max per level comes from the Lanczos tridiagonal of a few
+// Jacobi-preconditioned CG steps.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -132,28 +136,27 @@ void estimate_lambda(mfsem_mg& mg, mfsem_mg_level& L, int level, double* scratch
   }
 }
 
+// The smoother applies the degree-k Chebyshev polynomial of the interval
+// [lo, hi] to D^{-1} A, which equals the product of k damped-Jacobi steps
+// x += w_j D^{-1} (b - A x) with w_j = 1 / r_j over the polynomial's roots
+// r_j = theta + delta cos((2j+1) pi / (2k)).  After the k steps the iterate is
+// the same as the three-term recurrence's; the steps carry no direction vector,
+// so each reads x, b, A x and D^{-1} and writes x (two vectors fewer than the
+// recurrence).  The roots are taken from the largest down: every partial
+// product then stays within [-1, 1] on [0, hi] (no intermediate growth).
+// coef[j][b] = (0, w_j).
 void cheb_coefficients(const mfsem_mg& mg, const mfsem_mg_level& L, std::vector<double>& out) {
   const int B = mg.batch;
-  out.assign((size_t)L.steps * B * 2, 0.0);
+  const int k = L.steps;
+  out.assign((size_t)k * B * 2, 0.0);
   for (int b = 0; b < B; ++b) {
     const double lmax = L.lam[b];
     const double lo = mg.d.lo_frac * lmax, hi = mg.d.hi_frac * lmax;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
-    const double sig = theta / delta;
-    double rho = 1.0 / sig;
-    for (int j = 0; j < L.steps; ++j) {
-      double c1, c2;
-      if (j == 0) {
-        c1 = 0.0;
-        c2 = 1.0 / theta;
-      } else {
-        const double rn = 1.0 / (2.0 * sig - rho);
-        c1 = rn * rho;
-        c2 = 2.0 * rn / delta;
-        rho = rn;
-      }
-      out[((size_t)j * B + b) * 2] = c1;
-      out[((size_t)j * B + b) * 2 + 1] = c2;
+    for (int j = 0; j < k; ++j) {
+      const double r = theta + delta * std::cos((2.0 * j + 1.0) * M_PI / (2.0 * k));
+      out[((size_t)j * B + b) * 2] = 0.0;
+      out[((size_t)j * B + b) * 2 + 1] = 1.0 / r;
     }
   }
 }
@@ -184,16 +187,15 @@ void smooth(const mfsem_mg& mg, const mfsem_mg_level& L, T* b, T* x, bool from_z
             bool clear_b, hipStream_t s) {
   const int B = mg.batch;
   T* t = P_<T>(L.t);
-  T* d = P_<T>(L.d);
   const T* dinv = P_<T>(L.dinv);
   for (int j = 0; j < L.steps; ++j) {
     const double* c = L.coef + (size_t)j * B * 2;
     const bool last = j + 1 == L.steps;
     if (j == 0 && from_zero) {
-      vcheb<T>(x, d, b, nullptr, dinv, L.n, B, c, true, false, clear_b && last, s);
+      vjacobi<T>(x, b, nullptr, dinv, L.n, B, c, true, false, clear_b && last, s);
     } else {
       launch_apply<T>(*L.op, x, t, L.op->alpha, true, s, true);
-      vcheb<T>(x, d, b, t, dinv, L.n, B, c, false, true, clear_b && last, s);
+      vjacobi<T>(x, b, t, dinv, L.n, B, c, false, true, clear_b && last, s);
     }
   }
 }

@@ -218,6 +218,27 @@ __global__ __launch_bounds__(VT) void cheb_kernel(T* __restrict__ x, T* __restri
   }
 }
 
+// Damped-Jacobi step of the factored Chebyshev smoother:
+// x = (overwrite ? 0 : x) + w dinv (b - t), w = coef[bt*2 + 1]; flags as for
+// cheb_kernel (2 = clear t after use, 4 = clear b after use).
+template <typename T>
+__global__ __launch_bounds__(VT) void jacobi_kernel(T* __restrict__ x, T* __restrict__ b,
+                                                    T* __restrict__ t, const T* __restrict__ dinv,
+                                                    int64_t n, const double* __restrict__ coef,
+                                                    int flags) {
+  const int bt = blockIdx.y;
+  const int64_t off = (int64_t)bt * n;
+  const T w = (T)coef[bt * 2 + 1];
+  for (int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+    const T bv = b[off + i];
+    const T r = t ? bv - t[off + i] : bv;
+    const T dv = w * dinv[off + i] * r;
+    x[off + i] = (flags & 1) ? dv : x[off + i] + dv;
+    if (t && (flags & 2)) t[off + i] = T(0);
+    if (flags & 4) b[off + i] = T(0);
+  }
+}
+
 // y += x, then x = 0 when clear_x
 template <typename T>
 __global__ void axpy_kernel(T* __restrict__ y, T* __restrict__ x, int64_t n, int clear_x) {
@@ -333,6 +354,14 @@ void vcheb(T* x, T* d, T* b, T* t, const T* dinv, int64_t n, int batch, const do
 }
 
 template <typename T>
+void vjacobi(T* x, T* b, T* t, const T* dinv, int64_t n, int batch, const double* coef,
+             bool overwrite, bool clear_t, bool clear_b, hipStream_t s) {
+  const int flags = (overwrite ? 1 : 0) | (clear_t ? 2 : 0) | (clear_b ? 4 : 0);
+  jacobi_kernel<T><<<dim3(grid_for(n), batch), VT, 0, s>>>(x, b, t, dinv, n, coef, flags);
+  MFSEM_LAUNCH("jacobi_kernel");
+}
+
+template <typename T>
 void vaxpy(T* y, T* x, int64_t n, bool clear_x, hipStream_t s) {
   if (n <= 0) return;
   axpy_kernel<T><<<grid_for(n), VT, 0, s>>>(y, x, n, clear_x ? 1 : 0);
@@ -372,6 +401,8 @@ void vrandom(double* x, int64_t n, uint64_t seed, hipStream_t s) {
   template void vcheb<T>(T*, T*, T*, T*, const T*, int64_t, int, const double*, bool, bool,  \
                          bool, hipStream_t);                                                 \
   template void vaxpy<T>(T*, T*, int64_t, bool, hipStream_t);                                \
+  template void vjacobi<T>(T*, T*, T*, const T*, int64_t, int, const double*, bool, bool,    \
+                           bool, hipStream_t);                                               \
   template void vinvert<T>(T*, int64_t, hipStream_t);                                       \
   template void vlin<T>(T*, const T*, int64_t, int, const double*, hipStream_t);              \
   template void vmul<T>(T*, const T*, const T*, int64_t, int, hipStream_t);

@@ -36,6 +36,11 @@ void vp(double* p, const TZ* z, int64_t n, int batch, const PcgScalars* sc, hipS
 template <typename T>
 void vcheb(T* x, T* d, T* b, T* t, const T* dinv, int64_t n, int batch, const double* coef,
            bool overwrite, bool clear_t, bool clear_b, hipStream_t s);
+// x = (overwrite ? 0 : x) + w dinv (b - t) with w = coef[bt][1] (t may be
+// null); clear_t / clear_b set t / b to zero after they are read
+template <typename T>
+void vjacobi(T* x, T* b, T* t, const T* dinv, int64_t n, int batch, const double* coef,
+             bool overwrite, bool clear_t, bool clear_b, hipStream_t s);
 // y += x, then x = 0 when clear_x
 template <typename T>
 void vaxpy(T* y, T* x, int64_t n, bool clear_x, hipStream_t s);
