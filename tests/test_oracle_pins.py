@@ -474,6 +474,38 @@ def test_chebyshev_error_polynomial(k):
     np.testing.assert_allclose(xs - x, fac * xs, atol=1e-13)
 
 
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6])
+def test_chebyshev_equals_damped_jacobi_over_its_roots(k):
+    """The degree-k Chebyshev smoother is also the product of k damped-Jacobi
+    steps with weights 1/r over the roots r of its polynomial (the factored form
+    the GPU smoother runs): after k steps both reach the same iterate, from zero
+    and from a nonzero start, with a non-identity diagonal; taken from the
+    largest root down, no partial product exceeds 1 in magnitude on [0, hi]."""
+    rng = np.random.default_rng(k)
+    Q, _ = np.linalg.qr(rng.standard_normal((30, 30)))
+    A = Q @ np.diag(np.linspace(0.1, 3.0, 30)) @ Q.T
+    A = A + np.diag(np.linspace(1.0, 2.0, 30))
+    dinv = 1.0 / np.diag(A)
+    Dh = np.diag(np.sqrt(dinv))
+    lmax = np.linalg.eigvalsh(Dh @ A @ Dh).max()
+    lo, hi = 0.08 * lmax, 1.2 * lmax
+    th, de = (hi + lo) / 2, (hi - lo) / 2
+    roots = [th + de * np.cos((2 * j + 1) * np.pi / (2 * k)) for j in range(k)]
+    assert all(roots[j] > roots[j + 1] for j in range(k - 1))
+    b = synth.uniform(11, 30)
+    for x0 in (None, synth.uniform(12, 30)):
+        ref = solvers.chebyshev(A, dinv, b, x0, lmax, k)
+        x = np.zeros(30) if x0 is None else x0.copy()
+        for r in roots:
+            x = x + (1.0 / r) * dinv * (b - A @ x)
+        np.testing.assert_allclose(x, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    lam = np.linspace(0.0, hi, 501)
+    prod = np.ones_like(lam)
+    for r in roots:
+        prod = prod * (1 - lam / r)
+        assert np.abs(prod).max() <= 1.0 + 1e-12
+
+
 def test_vcycle_is_symmetric_positive():
     spec = synth.slab(4, (4, 2, 2))
     levels, transfers = [], []
