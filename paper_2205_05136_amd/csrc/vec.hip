@@ -196,31 +196,10 @@ __global__ __launch_bounds__(VT) void p_kernel(double* __restrict__ p, const TZ*
     p[off + i] = (be != 0.0) ? (double)z[off + i] + be * p[off + i] : (double)z[off + i];
 }
 
-// Chebyshev step: d = c1*d + c2*dinv*(b - t); x = (overwrite ? d : x + d).
-// flags: 1 = overwrite x, 2 = clear t after use (the next A x accumulates into
-// it), 4 = clear b after use (its last read in this V-cycle)
-template <typename T>
-__global__ __launch_bounds__(VT) void cheb_kernel(T* __restrict__ x, T* __restrict__ d,
-                                                  T* __restrict__ b, T* __restrict__ t,
-                                                  const T* __restrict__ dinv, int64_t n,
-                                                  const double* __restrict__ coef, int flags) {
-  const int bt = blockIdx.y;
-  const int64_t off = (int64_t)bt * n;
-  const T c1 = (T)coef[bt * 2], c2 = (T)coef[bt * 2 + 1];
-  for (int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
-    const T bv = b[off + i];
-    const T r = t ? bv - t[off + i] : bv;
-    const T dv = (c1 != T(0) ? c1 * d[off + i] : T(0)) + c2 * dinv[off + i] * r;
-    d[off + i] = dv;
-    x[off + i] = (flags & 1) ? dv : x[off + i] + dv;
-    if (t && (flags & 2)) t[off + i] = T(0);
-    if (flags & 4) b[off + i] = T(0);
-  }
-}
-
 // Damped-Jacobi step of the factored Chebyshev smoother:
 // x = (overwrite ? 0 : x) + w dinv (b - t), w = coef[bt*2 + 1]; flags as for
-// cheb_kernel (2 = clear t after use, 4 = clear b after use).
+// flags: 1 = overwrite x, 2 = clear t after use (the next A x accumulates into
+// it), 4 = clear b after use (its last read in this V-cycle).
 template <typename T>
 __global__ __launch_bounds__(VT) void jacobi_kernel(T* __restrict__ x, T* __restrict__ b,
                                                     T* __restrict__ t, const T* __restrict__ dinv,
@@ -346,14 +325,6 @@ void vp(double* p, const TZ* z, int64_t n, int batch, const PcgScalars* sc, hipS
 }
 
 template <typename T>
-void vcheb(T* x, T* d, T* b, T* t, const T* dinv, int64_t n, int batch, const double* coef,
-           bool overwrite, bool clear_t, bool clear_b, hipStream_t s) {
-  const int flags = (overwrite ? 1 : 0) | (clear_t ? 2 : 0) | (clear_b ? 4 : 0);
-  cheb_kernel<T><<<dim3(grid_for(n), batch), VT, 0, s>>>(x, d, b, t, dinv, n, coef, flags);
-  MFSEM_LAUNCH("cheb_kernel");
-}
-
-template <typename T>
 void vjacobi(T* x, T* b, T* t, const T* dinv, int64_t n, int batch, const double* coef,
              bool overwrite, bool clear_t, bool clear_b, hipStream_t s) {
   const int flags = (overwrite ? 1 : 0) | (clear_t ? 2 : 0) | (clear_b ? 4 : 0);
@@ -398,8 +369,6 @@ void vrandom(double* x, int64_t n, uint64_t seed, hipStream_t s) {
   template void vdot2<T, T>(const T*, const T*, const T*, int64_t, int, double*, double*,    \
                             hipStream_t, PcgScalars*, int);                                  \
   template void vp<T>(double*, const T*, int64_t, int, const PcgScalars*, hipStream_t);      \
-  template void vcheb<T>(T*, T*, T*, T*, const T*, int64_t, int, const double*, bool, bool,  \
-                         bool, hipStream_t);                                                 \
   template void vaxpy<T>(T*, T*, int64_t, bool, hipStream_t);                                \
   template void vjacobi<T>(T*, T*, T*, const T*, int64_t, int, const double*, bool, bool,    \
                            bool, hipStream_t);                                               \

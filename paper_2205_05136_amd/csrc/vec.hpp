@@ -31,11 +31,6 @@ void vxr(double* x, double* r, float* r32, const double* p, double* q, int64_t n
 // p = z + beta p (p = z when beta == 0); z in FP64 or FP32
 template <typename TZ>
 void vp(double* p, const TZ* z, int64_t n, int batch, const PcgScalars* sc, hipStream_t s);
-// d = c1 d + c2 dinv (b - t); x = overwrite ? d : x + d   (coef [batch][2]);
-// clear_t / clear_b set t / b to zero after they are read
-template <typename T>
-void vcheb(T* x, T* d, T* b, T* t, const T* dinv, int64_t n, int batch, const double* coef,
-           bool overwrite, bool clear_t, bool clear_b, hipStream_t s);
 // x = (overwrite ? 0 : x) + w dinv (b - t) with w = coef[bt][1] (t may be
 // null); clear_t / clear_b set t / b to zero after they are read
 template <typename T>
