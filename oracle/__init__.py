@@ -19,8 +19,10 @@ What it computes, and from where in the paper (arXiv 2205.05136):
                  (Sections 4.3 and 5), fast diagonalisation (textbook)
   multigrid.py   p- and octree h-prolongation as explicit sparse matrices (Section 4.3)
   adjoint.py     dL/dsigma per element through the solve (not in the paper)
-  ionic.py       Aliev-Panfilov IMEX step and pointwise RHS (stand-in for the
-                 paper's cited ionic models); parity unpinned against paper values
+  ionic.py       Aliev-Panfilov IMEX and BDF2 steps and pointwise RHS (stand-in
+                 for the paper's cited ionic models; parity unpinned against
+                 paper values), activation times as the time of the largest
+                 |dV/dt| (Section 5.1)
 
 Every function is plain and slow on purpose: element matrices are dense
 (P^3 x P^3) and nothing is sum-factorised, blocked or fused.

@@ -82,11 +82,55 @@ def bdf2_rhs_and_gate(V, V_old, w, w_old, i_stim, mass_diag, dt, chi, cm, prm):
     return b, w_next
 
 
-def activation_update(act, V_old, V, t_old, t_new, v_act):
-    """First crossing of v_act by the potential at every DOF, linearly
-    interpolated in time between two steps; act < 0 marks 'not yet'."""
+def activation_times(V_series, t_series):
+    """Activation time at every DOF from a whole time series (Section 5.1, the
+    activation-time definition: the instant at which the potential changes
+    fastest, tau(x_i) = argmax_t |du/dt(x_i, t)|).
+
+    V_series [n_steps+1][n_dof] holds V at the times t_series [n_steps+1].  The
+    derivative over step n is the difference quotient (V^{n+1} - V^n) /
+    (t^{n+1} - t^n), a second-order estimate of du/dt at the step's midpoint,
+    so tau is that midpoint for the step with the largest |quotient|; on ties
+    the earliest step wins.  A DOF whose potential never changes keeps -1.
+    Returns (tau, largest |du/dt|)."""
+    V = np.asarray(V_series, dtype=np.float64)
+    t = np.asarray(t_series, dtype=np.float64)
+    n_dof = V.shape[1]
+    tau = np.full(n_dof, -1.0)
+    rate = np.zeros(n_dof)
+    for i in range(n_dof):
+        for n in range(len(t) - 1):
+            r = abs(V[n + 1, i] - V[n, i]) / (t[n + 1] - t[n])
+            if r > rate[i]:
+                rate[i] = r
+                tau[i] = t[n] + 0.5 * (t[n + 1] - t[n])
+    return tau, rate
+
+
+def activation_update(act, rate, V_old, V, t_old, t_new):
+    """The same definition kept as a running maximum, one step at a time (the
+    form a time loop can afford): where |V - V_old| / (t_new - t_old) exceeds
+    rate, rate takes it and act the step's midpoint.  Start from act = -1 and
+    rate = 0; after the last step act equals activation_times over the series.
+    Returns new (act, rate)."""
     act = np.array(act, dtype=np.float64, copy=True)
+    rate = np.array(rate, dtype=np.float64, copy=True)
+    dt = t_new - t_old
     for i in range(len(act)):
-        if act[i] < 0.0 and V_old[i] < v_act <= V[i]:
-            act[i] = t_old + (t_new - t_old) * (v_act - V_old[i]) / (V[i] - V_old[i])
-    return act
+        r = abs(V[i] - V_old[i]) / dt
+        if r > rate[i]:
+            rate[i] = r
+            act[i] = t_old + 0.5 * dt
+    return act, rate
+
+
+def threshold_crossing_update(cross, V_old, V, t_old, t_new, v_cross):
+    """First upward crossing of the level v_cross at every DOF, linearly
+    interpolated in time between two steps; cross < 0 marks 'not yet'.  Not the
+    paper's activation time (which is the steepest point of the upstroke, later
+    than a crossing below it); kept as a separately named output."""
+    cross = np.array(cross, dtype=np.float64, copy=True)
+    for i in range(len(cross)):
+        if cross[i] < 0.0 and V_old[i] < v_cross <= V[i]:
+            cross[i] = t_old + (t_new - t_old) * (v_cross - V_old[i]) / (V[i] - V_old[i])
+    return cross

@@ -555,7 +555,7 @@ def test_ionic_bdf2_step():
     b_ref, w_ref = oion.bdf2_rhs_and_gate(V, Vo, w, wo, ist, m, dt, synth.CHI, synth.CM,
                                           synth.AP_PARAMS)
     act0 = np.where(synth.uniform(19, n) > 0.5, -1.0, 1.25)
-    act_ref = oion.activation_update(act0, Vo, V, t - dt, t, v_act)
+    act_ref = oion.threshold_crossing_update(act0, Vo, V, t - dt, t, v_act)
     wd, wod, actd = to_dev(w), to_dev(wo), to_dev(act0)
     b = mf.ap_bdf2_rhs(to_dev(V), to_dev(Vo), wd, wod, to_dev(m), dt, synth.CHI, synth.CM,
                        synth.AP_PARAMS, i_stim=to_dev(ist), t=t, v_act=v_act, act=actd)

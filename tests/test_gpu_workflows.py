@@ -148,7 +148,7 @@ def test_monodomain_bdf2_matches_oracle():
     Ainv = spla.factorized(A.tocsc())
     t = 0.0
     for n in range(60):
-        act = oion.activation_update(act, Vo, V, t - dt, t, -40.0)
+        act = oion.threshold_crossing_update(act, Vo, V, t - dt, t, -40.0)
         b, w_new = oion.bdf2_rhs_and_gate(V, Vo, w, wo, istim if t + dt <= dur else 0 * istim, m,
                                           dt, synth.CHI, synth.CM, prm)
         wo, w = w, w_new

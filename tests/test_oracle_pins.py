@@ -528,6 +528,92 @@ def test_vcycle_is_symmetric_positive():
     assert it < 25
 
 
+def _smoother_matrix(A, dinv, lam, k):
+    """The pre-smoother from zero as an explicit matrix S (x = S b), column by
+    column from the oracle's Chebyshev routine (pinned above by its closed-form
+    error polynomial)."""
+    n = A.shape[0]
+    return np.stack([solvers.chebyshev(A, dinv, e, None, lam, k) for e in np.eye(n)], axis=1)
+
+
+def _exact_cycle_hierarchy(A0, b, x_star, k, rng, m1=6):
+    """Levels and transfers on which a correct V-cycle returns the exact
+    solution x* of A0 x = b (b = A0 x*), by construction:
+      * level 0 -> 1: the first column of P0 is the error left by pre-smoothing,
+        (I - S0 A0) x*; the rest are random.  A1 = P0^T A0 P0 (Galerkin).
+      * level 1 -> 2: the restricted residual is g = P0^T (b - A0 S0 b), whose
+        exact coarse solution y* = A1^{-1} g is in the coarse space; P1 is the
+        single column (I - S1 A1) y*, the error pre-smoothing leaves on level 1.
+      * level 2 is 1x1 with lambda = 1/0.64: Chebyshev of degree 1 from zero is
+        then D^{-1} b / theta with theta = 1, i.e. the exact solve.
+    Pre-smoothing leaves an error in the range of the prolongation, the exact
+    coarse correction removes it, and post-smoothing keeps the exact solution."""
+    n0 = A0.shape[0]
+    d0 = 1.0 / np.diag(A0)
+    lam0 = np.linalg.eigvals(d0[:, None] * A0).real.max()
+    S0 = _smoother_matrix(A0, d0, lam0, k)
+    P0 = np.column_stack([x_star - S0 @ (A0 @ x_star), rng.standard_normal((n0, m1 - 1))])
+    A1 = P0.T @ A0 @ P0
+    d1 = 1.0 / np.diag(A1)
+    lam1 = np.linalg.eigvals(d1[:, None] * A1).real.max()
+    S1 = _smoother_matrix(A1, d1, lam1, k)
+    g = P0.T @ (b - A0 @ (S0 @ b))
+    y_star = np.linalg.solve(A1, g)
+    P1 = (y_star - S1 @ (A1 @ y_star))[:, None]
+    A2 = P1.T @ A1 @ P1
+    levels = [(A0, d0, lam0), (A1, d1, lam1), (A2, 1.0 / np.diag(A2), 1.0 / 0.64)]
+    return levels, [P0, P1]
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_vcycle_coarse_correction_is_exact_on_a_constructed_hierarchy(k):
+    """Section 4.3's V-cycle: smooth, restrict the residual, correct with the
+    prolongated coarse solution, smooth again.  On the hierarchy built by
+    _exact_cycle_hierarchy every step is exact, so one cycle from zero returns
+    x*; dropping, mis-scaling or mis-signing the coarse correction, restricting
+    b instead of the residual, or skipping a level would leave an error of the
+    size of x*.  Two-level and three-level cycles on an SPD matrix from the
+    assembled operator."""
+    spec = synth.slab(2, (2, 2, 1))
+    A0 = operator.Problem(spec).assemble()[0].toarray()
+    rng = np.random.default_rng(17 + k)
+    x_star = rng.standard_normal(A0.shape[0])
+    b = A0 @ x_star
+    levels, transfers = _exact_cycle_hierarchy(A0, b, x_star, k, rng)
+    x = solvers.vcycle(levels, transfers, b, k, 1)
+    np.testing.assert_allclose(x, x_star, rtol=0, atol=1e-9 * np.abs(x_star).max())
+    # two levels: level 1 solved exactly by making it the 1x1 coarsest level of a
+    # hierarchy whose single coarse vector is the error pre-smoothing leaves
+    d0, lam0 = levels[0][1], levels[0][2]
+    S0 = _smoother_matrix(A0, d0, lam0, k)
+    P = (x_star - S0 @ (A0 @ x_star))[:, None]
+    Ac = P.T @ A0 @ P
+    two = [levels[0], (Ac, 1.0 / np.diag(Ac), 1.0 / 0.64)]
+    x2 = solvers.vcycle(two, [P], b, k, 1)
+    np.testing.assert_allclose(x2, x_star, rtol=0, atol=1e-9 * np.abs(x_star).max())
+
+
+def test_vcycle_beats_the_smoother_alone():
+    """With a small mass coefficient the Jacobi-Chebyshev smoother alone leaves
+    the smooth error: as a CG preconditioner it needs several times the
+    iterations of the V-cycle on the p 4 -> 2 -> 1 hierarchy (Section 5 reports
+    1.4-2.1 GMG iterations per solve, independent of h and p)."""
+    spec = synth.slab(4, (8, 3, 2)).with_(alpha=0.01)
+    levels = []
+    for pl in (4, 2, 1):
+        A = operator.Problem(spec, dof_p=pl).assemble()[0]
+        dinv = 1 / A.diagonal()
+        levels.append((A, dinv, solvers.lanczos_lambda_max(A, dinv, synth.uniform(9, A.shape[0]))))
+    transfers = [multigrid.prolongation_p(spec.n, 4, 2), multigrid.prolongation_p(spec.n, 2, 1)]
+    A, dinv, lam = levels[0]
+    b = synth.uniform(3, A.shape[0])
+    _, it_mg, _ = solvers.cg(A, b, rtol=1e-10, M=lambda r: solvers.vcycle(levels, transfers, r, 3, 6))
+    sym = lambda r: solvers.chebyshev(A, dinv, b=r, x0=solvers.chebyshev(A, dinv, r, None, lam, 3),
+                                      lam_max=lam, degree=3)
+    _, it_sm, _ = solvers.cg(A, b, rtol=1e-10, M=sym)
+    assert it_mg <= 20 and it_sm >= 3 * it_mg, (it_mg, it_sm)
+
+
 # --- adjoint --------------------------------------------------------------------
 
 def test_linearity_in_sigma_and_adjoint_fd():
@@ -650,11 +736,92 @@ def test_bdf2_gate_linear_case_and_rest_state():
     assert np.allclose(b, 2.0 * 1.5 * synth.CHI * synth.CM / dt * prm["v_rest"], rtol=1e-15)
 
 
-def test_activation_time_interpolation():
-    """A linear ramp V(t) = -100 + 10 t crosses -40 mV at t = 6 exactly."""
-    t = np.arange(0.0, 10.01, 0.3)
-    V = -100.0 + 10.0 * t
-    act = np.full(1, -1.0)
-    for n in range(1, len(t)):
-        act = ionic.activation_update(act, V[n - 1:n], V[n:n + 1], t[n - 1], t[n], -40.0)
-    assert abs(act[0] - 6.0) < 1e-12
+def _tanh_series(n_steps, m, dt, width, amp, base=0.0, half=True):
+    """V_n = base + amp tanh(s_n), s_n = (n - m - 1/2) dt / width (half=True: the
+    steepest point sits at the midpoint of step m) or (n - m) dt / width (half=False:
+    on the sample t_m, so steps m-1 and m are equally steep).  Built from |s| so
+    that V is exactly antisymmetric about its centre whatever tanh's rounding."""
+    k = np.arange(n_steps + 1) - m - (0.5 if half else 0.0)
+    mag = amp * np.tanh(np.abs(k) * dt / width)
+    return base + np.where(k < 0, -mag, mag)
+
+
+def test_activation_time_is_steepest_point_of_tanh_upstrokes():
+    """Section 5.1: tau = argmax_t |du/dt|.  For V = base + amp tanh((t - t0)/w)
+    sampled every dt with t0 half-way between two samples, the steepest step is
+    the one centred on the inflection point t0, so tau = t0 exactly; this holds
+    for downstrokes (amp < 0) as for upstrokes, and on a DOF with a gentle
+    upstroke followed by a steeper downstroke the downstroke wins."""
+    dt, n_steps = 0.05, 200
+    t = np.arange(n_steps + 1) * dt
+    cols, tau_exact = [], []
+    for m, w, amp, base in [(40, 0.2, 50.0, -35.0), (123, 0.9, 50.0, -35.0),
+                            (7, 0.05, -60.0, 0.0), (170, 3.0, 1.0, -80.0)]:
+        cols.append(_tanh_series(n_steps, m, dt, w, amp, base))
+        tau_exact.append((m + 0.5) * dt)
+    up = _tanh_series(n_steps, 30, dt, 1.0, 20.0)       # gentle upstroke at step 30
+    down = _tanh_series(n_steps, 150, dt, 0.1, -45.0)   # steep downstroke at step 150
+    cols.append(up + down)
+    tau_exact.append(150.5 * dt)
+    V = np.stack(cols, axis=1)
+    tau, rate = ionic.activation_times(V, t)
+    np.testing.assert_allclose(tau, tau_exact, rtol=0, atol=1e-12)
+    # the largest rate is the difference quotient over the centred step
+    assert abs(rate[0] - 2 * 50.0 * np.tanh(0.5 * dt / 0.2) / dt) < 1e-9
+    # the crossing of a level below the inflection point comes earlier
+    cross = np.full(V.shape[1], -1.0)
+    for n in range(n_steps):
+        cross = ionic.threshold_crossing_update(cross, V[n], V[n + 1], t[n], t[n + 1], -40.0)
+    t_cross = tau_exact[0] - 0.2 * np.arctanh(0.1)
+    assert abs(cross[0] - t_cross) < 0.5 * dt and cross[0] < tau[0] - 0.01
+
+
+def test_activation_time_ties_take_the_first_step():
+    """With the inflection point on a sample, the two steps around it have
+    exactly equal |dV| (V is antisymmetric about it), and the earlier one is
+    the activation step; a constant potential has no activation time.  The
+    step is a power of two, so the time grid is exact and so are the ties."""
+    dt, n_steps, m = 0.125, 60, 25
+    t = np.arange(n_steps + 1) * dt
+    V = np.stack([_tanh_series(n_steps, m, dt, 0.3, 40.0, half=False),
+                  np.full(n_steps + 1, -80.0)], axis=1)
+    q = np.abs(np.diff(V[:, 0])) / np.diff(t)
+    assert q[m - 1] == q[m] == q.max()
+    tau, rate = ionic.activation_times(V, t)
+    assert abs(tau[0] - (m - 0.5) * dt) < 1e-12
+    assert tau[1] == -1.0 and rate[1] == 0.0
+
+
+def test_activation_running_form_equals_series_form_and_brute_force():
+    """The one-step running maximum equals the whole-series definition, and
+    both equal numpy's argmax (first occurrence) of |diff V| over random series
+    with repeated values (ties) and a non-uniform time grid."""
+    rng = np.random.default_rng(5)
+    n_steps, n = 40, 300
+    t = np.cumsum(np.r_[0.0, rng.uniform(0.5, 1.5, n_steps)]) * 0.01
+    V = np.round(rng.normal(size=(n_steps + 1, n)) * 3) * 2.0  # small integers: many ties
+    tau, rate = ionic.activation_times(V, t)
+    act, r = np.full(n, -1.0), np.zeros(n)
+    for k in range(n_steps):
+        act, r = ionic.activation_update(act, r, V[k], V[k + 1], t[k], t[k + 1])
+    assert np.array_equal(act, tau) and np.array_equal(r, rate)
+    q = np.abs(np.diff(V, axis=0)) / np.diff(t)[:, None]
+    k = np.argmax(q, axis=0)
+    mid = 0.5 * (t[:-1] + t[1:])
+    moved = q.max(axis=0) > 0
+    np.testing.assert_allclose(tau[moved], mid[k[moved]], rtol=0, atol=1e-15)
+    assert np.all(tau[~moved] == -1.0)
+
+
+def test_activation_time_converges_to_the_inflection_point():
+    """For a smooth upstroke whose steepest point t* falls between samples, the
+    discrete activation time is within dt/2 of t* and approaches it as dt -> 0."""
+    ts = 1.2345
+    f = lambda t: -80.0 + 50.0 * (1.0 + np.tanh((t - ts) / 0.07))
+    errs = []
+    for dt in (0.04, 0.02, 0.01, 0.005):
+        t = np.arange(0.0, 3.0 + dt / 2, dt)
+        tau, _ = ionic.activation_times(f(t)[:, None], t)
+        errs.append(abs(tau[0] - ts))
+        assert errs[-1] <= 0.5 * dt + 1e-12
+    assert errs[-1] < errs[0]
