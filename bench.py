@@ -1,13 +1,16 @@
-"""Benchmark of the matrix-free SEM-NI operator and its GMG-PCG solve on one GPU.
+"""Benchmark of the matrix-free SEM / SEM-NI operator and its GMG-PCG solve on one GPU.
 
-Default workload: the sheared slab 20 x 7 x 3 mm with 40 x 14 x 6 hexahedra at
-p = 4, GLL quadrature (SEM-NI), anisotropic rotating-fiber conductivity,
-alpha = chi*Cm/dt = 28 (229,425 DOFs); FP64 apply and GMG-PCG with
-p-coarsening 4 -> 2 -> 1 and Chebyshev degree 3, random right-hand side.
+Default workload: the sheared slab 20 x 7 x 3 mm at about 51M DOFs and p = 4
+(224 x 84 x 42 hexahedra, 51,243,525 DOFs), GLL quadrature (SEM-NI),
+anisotropic rotating-fiber conductivity, alpha = chi*Cm/dt = 28; FP64 apply and
+GMG-PCG with p-coarsening 4 -> 2 -> 1 and Chebyshev degree 3, random
+right-hand side.  Every apply moves about 6 GB, far beyond the 256 MB Infinity
+Cache, so the rates are HBM rates.
 
 One timed step = one pass of the hot path on that input:
-  * R back-to-back operator applies y = A x (FP64; --apply-reps, default 100),
-    then R launches of the kernel alone (y += A x) in FP64 and in FP32,
+  * R back-to-back operator applies y = A x (FP64; --apply-reps, default 20 on
+    meshes above 4M DOFs, else 100), then R launches of the kernel alone
+    (y += A x) in FP64 and in FP32,
   * one FP64 GMG-PCG solve A u = f to ||r||/||f|| <= 1e-10 from u0 = 0,
   * one mixed-precision solve (FP32 V-cycle inside FP64 flexible CG), same tolerance.
 `value` is the apply throughput in GDOF/s (unique mesh nodes per second) from
@@ -15,8 +18,22 @@ HIP events around the back-to-back applies inside the timed steps; the PCG
 times are reported beside it.  Set-up (geometry, diagonals, eigenvalue
 estimates) is outside the timed region, as in the paper.
 
+After the timed steps, the same JSON line carries (default run, --no-sweep to skip):
+  sweep      the metric over p = 2..7 on the ~51M-DOF slab: FP64 and FP32 kernel
+             times, y = A x, PCG time-to-1e-10 FP64 vs mixed with iterations,
+             each solve's byte model per iteration and its HBM fraction, and
+             its error against the FP64 oracle (sampled rows of b - A x with
+             the oracle's element matrices);
+  c3_gauss   the same for SEM (Gauss q = 9) at p = 7, 128 x 48 x 24 hexes;
+  c2         the 229,425-DOF c2 slab (cache-resident, latency-bound).
+`pcg_roofline` gives the main workload's solve against the HBM roofline: the
+algorithmic bytes of every kernel of one PCG iteration (V-cycle applies,
+smoother steps, transfer passes, CG vector kernels) divided by the measured
+time per iteration.
+
 Other workloads (--workload):
   slab-p{2..7}[-gauss]  the sheared slab refined to about 51M DOFs (p-sweep),
+  c2                    sheared slab, 40 x 14 x 6 hexes at p = 4 (229,425 DOFs),
   c3 / c3-gauss         128 x 48 x 24 hexes at p = 7, SEM-NI / SEM (q = 9),
   c2-p{1..8}            the c2 slab at another degree (the matrix-based comparison
                         per degree),
@@ -88,8 +105,10 @@ def algorithmic_flops(spec, n_elem, n_dof, quad):
 
 
 def measured_traffic(kernel, source, workload):
-    """HBM bytes per launch from the committed counter runs (profiles/counters.json),
-    or None when the kernel source changed since they were taken."""
+    """HBM bytes per launch from the committed counter runs (profiles/counters.json:
+    rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, each scaled by the same counter's
+    reading for a copy of known size), and a label saying where they come from.
+    The bytes are None when the kernel source changed since they were taken."""
     import hashlib
     src = os.path.join(ROOT, "paper_2205_05136_amd", "csrc", source)
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -97,10 +116,15 @@ def measured_traffic(kernel, source, workload):
         entry = json.load(open(os.path.join(ROOT, "profiles", "counters.json"))).get(
             f"{kernel}|{workload}")
     except (OSError, ValueError):
-        return None
-    if not entry or entry.get("source_sha") != sha:
-        return None
-    return int(entry["read_bytes"] + entry["write_bytes"])
+        entry = None
+    if not entry:
+        return None, "no counter run for this kernel and workload"
+    if entry.get("source_sha") != sha:
+        return None, (f"counters taken at kernel source sha {entry.get('source_sha')}, "
+                      f"current {sha}: not reported")
+    return (int(entry["read_bytes"] + entry["write_bytes"]),
+            f"not measured in this run: profiles/counters.json, rocprofv3 --pmc FETCH_SIZE and "
+            f"WRITE_SIZE (copy-calibrated) at {source} sha {sha}")
 
 
 # p-multigrid degree sequences, measured on the 51M-DOF slab (PCG to 1e-10, FP64 and
@@ -196,14 +220,115 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(spec, budget_s=20.0):
-    """The oracle's matrix-based apply (assembled CSR SpMV, SciPy, one thread)
-    on the same mesh, timed on the host cores."""
+def level_plan(spec, chain):
+    """(p, elements per axis, points per axis, quadrature) of every multigrid
+    level, finest first: p-steps lower the degree on the same elements, h-steps
+    halve the elements; levels below the finest are GLL (SEM-NI)."""
+    p, n = spec.p, tuple(spec.n)
+    levels = [(p, n, spec.q, spec.quad)]
+    for c in chain:
+        if c[0] == "p":
+            p = c[1]
+        else:
+            n = tuple(k // 2 for k in n)
+        levels.append((p, n, p + 1, "gll"))
+    return levels
+
+
+def _nodes(p, n):
+    return [p * k + 1 for k in n]
+
+
+def apply_bytes(p, n, q, quad, w):
+    """Algorithmic bytes of one y += A x launch on a level (apply_kernel's model)."""
+    ne = n[0] * n[1] * n[2]
+    N = math.prod(_nodes(p, n))
+    b = 3 * w * N + 6 * w * ne * q ** 3 + w * ne
+    return b + (4 * ne * (p + 1) ** 3 if quad != "gll" else 0)
+
+
+def pcg_bytes_model(spec, chain, degree, coarse_degree, mixed):
+    """Algorithmic bytes of the PCG solve, kernel by kernel, as the library
+    launches them: one iteration is one V-cycle (word size 4 when mixed, else
+    8), a dot product r.z (and r.z_old for the flexible CG of the mixed solve),
+    p = z + beta p, q = A p in FP64, a dot product p.q, and the x, r update
+    (which also clears q and, mixed, writes r in FP32).  Each V-cycle level
+    above the coarsest runs `degree` smoother steps before and after the
+    coarse correction (the first from zero, without a product; each other one
+    an apply y += A x and a damped-Jacobi step reading x, b, A x and D^-1 and
+    writing x and clearing A x), the residual apply, a three-pass restriction
+    (b - A x read, intermediate lattices written and read, the coarse b
+    written) and a three-pass prolongation (the last pass reads and writes x
+    and clears A x); the coarsest level runs `coarse_degree` steps from zero.
+    Levels below the finest clear their b on its last read.  Returns
+    {"iteration": bytes, "initial": bytes, "parts": {kernel group: bytes}}."""
+    w = 4 if mixed else 8
+    lv = level_plan(spec, chain)
+    parts = {}
+
+    def add(k, b):
+        parts[k] = parts.get(k, 0) + int(b)
+
+    for l, (p, n, q, quad) in enumerate(lv):
+        N = math.prod(_nodes(p, n))
+        A = apply_bytes(p, n, q, quad, w)
+        own_b = w * N if l > 0 else 0
+        if l == len(lv) - 1:
+            k = coarse_degree
+            add("vcycle_apply", (k - 1) * A)
+            add("vcycle_smoother", 3 * w * N + (k - 1) * 6 * w * N + own_b)
+            continue
+        k = degree
+        add("vcycle_apply", 2 * k * A)
+        add("vcycle_smoother", 3 * w * N + (2 * k - 1) * 6 * w * N + own_b)
+        F = _nodes(p, n)
+        C = _nodes(lv[l + 1][0], lv[l + 1][1])
+        s1, s2, Nc = F[0] * C[1] * C[2], F[0] * F[1] * C[2], math.prod(C)
+        add("restriction", w * (2 * N + 2 * s2 + 2 * s1 + Nc))
+        add("prolongation", w * (Nc + 2 * s1 + 2 * s2 + 3 * N))
+    N = spec.n_dof
+    add("cg_apply_fp64", apply_bytes(spec.p, spec.n, spec.q, spec.quad, 8))
+    add("cg_vectors", (8 + w + (w if mixed else 0)) * N   # r.z (and r.z_old)
+        + (w + 16) * N                                    # p = z + beta p
+        + 16 * N                                          # p.q
+        + (56 + (4 if mixed else 0)) * N)                 # x, r update, q cleared
+    initial = apply_bytes(spec.p, spec.n, spec.q, spec.quad, 8) + (32 + (4 if mixed else 0)) * N
+    return {"iteration": sum(parts.values()), "initial": int(initial), "parts": parts}
+
+
+def pcg_roofline(spec, chain, degree, ms, iters, mixed):
+    """The solve against the HBM roofline: modelled bytes of the whole solve
+    (initial residual + iterations) over its measured time."""
+    m = pcg_bytes_model(spec, chain, degree, 2 * degree, mixed)
+    total = m["initial"] + iters * m["iteration"]
+    achieved = total / (ms * 1e-3) / 1e9
+    return {"bytes_per_iteration": m["iteration"], "bytes_initial_residual": m["initial"],
+            "bytes_per_iteration_by_kernel": m["parts"],
+            "achieved_GBs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4)}
+
+
+def _median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def cpu_baseline(spec, budget_s=12.0):
+    """The oracle timed on the host cores, on bounded samples.
+
+    value: the oracle's own apply on the benchmark's workload, row by row
+    (dense element matrices of the elements around each DOF, as it stands,
+    one thread), scaled to GDOF/s; the full matrix of a 51M-DOF mesh would
+    not fit the host.  c2: the oracle's assembled CSR matrix of the c2 slab,
+    its product timed with SciPy on one thread and with torch's sparse CSR
+    on every host core (median of 5 runs each)."""
     import numpy as np
+    import torch
     import synth
+    from threadpoolctl import threadpool_limits
     from oracle import operator as oop
-    if spec.n_elem > 4000:
-        # too large to assemble: rows of A x one by one from the element matrices
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    out = {}
+    with threadpool_limits(1):
         x_fn = lambda g: np.sin(0.37 * np.asarray(g, dtype=np.float64))
         rng = np.random.default_rng(0)
         rows, t = 0, 0.0
@@ -213,60 +338,82 @@ def cpu_baseline(spec, budget_s=20.0):
             oop.apply_rows(spec, x_fn, g)
             t += time.perf_counter() - t1
             rows += len(g)
-        return {"value": rows / t / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+    out.update({"value": rows / t / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
                 "sample": (f"oracle row-by-row apply (dense element matrices of the elements "
-                           f"around each DOF) on {rows} random rows of the full mesh in {t:.1f} s; "
-                           f"assembling the full matrix at {spec.n_elem:,} elements is beyond "
-                           f"this baseline's time budget")}
-    t0 = time.perf_counter()
-    prob = oop.Problem(spec)
-    A, _, _ = prob.assemble()
-    t_asm = time.perf_counter() - t0
-    x = synth.uniform(100, prob.n_dof)
-    reps, t_spmv = 0, 0.0
-    while t_spmv < budget_s and reps < 200:
-        t1 = time.perf_counter()
-        A @ x
-        t_spmv += time.perf_counter() - t1
-        reps += 1
-    per = t_spmv / reps
-    return {"value": prob.n_dof / per / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle assembled-CSR SpMV (SciPy, single thread) on the full workload "
-                       f"mesh, {reps} applies in {t_spmv:.1f} s ({per * 1e3:.2f} ms each); "
-                       f"element-matrix assembly {t_asm:.1f} s excluded; host has "
-                       f"{os.cpu_count()} logical CPUs")}
+                           f"around each DOF, one thread) on {rows} random rows of the "
+                           f"benchmark's {spec.n_dof:,}-DOF mesh in {t:.1f} s, scaled to GDOF/s; "
+                           f"the host has {ncpu} cores")})
+    c2 = synth.C2
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        A, _, _ = oop.Problem(c2).assemble()
+        t_asm = time.perf_counter() - t0
+        x = synth.uniform(100, c2.n_dof)
+        t1 = []
+        for _ in range(5):
+            a = time.perf_counter()
+            A @ x
+            t1.append(time.perf_counter() - a)
+    nt = torch.get_num_threads()
+    torch.set_num_threads(ncpu)
+    try:
+        At = torch.sparse_csr_tensor(torch.as_tensor(A.indptr, dtype=torch.int64),
+                                     torch.as_tensor(A.indices, dtype=torch.int64),
+                                     torch.as_tensor(A.data), size=A.shape)
+        xt = torch.as_tensor(x)
+        At @ xt
+        tn = []
+        for _ in range(5):
+            a = time.perf_counter()
+            At @ xt
+            tn.append(time.perf_counter() - a)
+    finally:
+        torch.set_num_threads(nt)
+    m1, mn = _median(t1), _median(tn)
+    out["c2_csr_spmv"] = {
+        "n_dof": c2.n_dof, "nnz": int(A.nnz),
+        "scipy_1_thread": {"ms": round(m1 * 1e3, 3), "gdofs": round(c2.n_dof / m1 / 1e9, 5),
+                           "cores": 1},
+        "torch_csr_all_cores": {"ms": round(mn * 1e3, 3), "gdofs": round(c2.n_dof / mn / 1e9, 5),
+                                "cores": ncpu},
+        "assembly_s": round(t_asm, 1),
+        "sample": "the oracle's assembled matrix of the c2 slab (Alg. 2's matrix-based path), "
+                  "median of 5 products each; assembly excluded"}
+    return out
 
 
 def cpu_pcg_baseline(spec, chain, degree, max_dofs=1_000_000):
     """The oracle's GMG-PCG (explicit level matrices, prolongation matrices and
     V-cycle, the same chain and Chebyshev degrees, lambda_max by its own 10-step
-    Lanczos) to 1e-10 from zero on the workload's right-hand side, timed on the
-    host beside the GPU solve.  Only for meshes the oracle assembles in seconds."""
-    import numpy as np
+    Lanczos) to 1e-10 from zero on the workload's right-hand side, timed on one
+    host core.  Only for meshes the oracle assembles in seconds."""
     import synth
+    from threadpoolctl import threadpool_limits
     from oracle import multigrid as omg
     from oracle import operator as oop
     from oracle import solvers as osol
     if spec.n_dof > max_dofs or spec.quad != "gll" or any(c[0] != "p" for c in chain):
         return None
-    t0 = time.perf_counter()
-    mats, Ps, p = [oop.Problem(spec).assemble()[0]], [], spec.p
-    for c in chain:
-        mats.append(oop.Problem(spec, dof_p=c[1], quad="gll").assemble()[0])
-        Ps.append(omg.prolongation_p(spec.n, p, c[1]))
-        p = c[1]
-    levels = []
-    for A in mats:
-        dinv = 1.0 / A.diagonal()
-        levels.append((A, dinv, osol.lanczos_lambda_max(A, dinv, synth.uniform(7, A.shape[0]))))
-    t_setup = time.perf_counter() - t0
-    f = synth.uniform(2, spec.n_dof)
-    t1 = time.perf_counter()
-    x, it, rn = osol.cg(mats[0], f, rtol=1e-10,
-                        M=lambda r: osol.vcycle(levels, Ps, r, degree, 2 * degree))
-    t_solve = time.perf_counter() - t1
-    return {"kind": "oracle", "cores": 1, "time_to_1e-10_ms": round(t_solve * 1e3, 1),
-            "iterations": it, "setup_s": round(t_setup, 1),
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        mats, Ps, p = [oop.Problem(spec).assemble()[0]], [], spec.p
+        for c in chain:
+            mats.append(oop.Problem(spec, dof_p=c[1], quad="gll").assemble()[0])
+            Ps.append(omg.prolongation_p(spec.n, p, c[1]))
+            p = c[1]
+        levels = []
+        for A in mats:
+            dinv = 1.0 / A.diagonal()
+            levels.append((A, dinv, osol.lanczos_lambda_max(A, dinv, synth.uniform(7, A.shape[0]))))
+        t_setup = time.perf_counter() - t0
+        f = synth.uniform(2, spec.n_dof)
+        t1 = time.perf_counter()
+        x, it, rn = osol.cg(mats[0], f, rtol=1e-10,
+                            M=lambda r: osol.vcycle(levels, Ps, r, degree, 2 * degree))
+        t_solve = time.perf_counter() - t1
+    return {"kind": "oracle", "cores": 1, "n_dof": spec.n_dof,
+            "time_to_1e-10_ms": round(t_solve * 1e3, 1), "iterations": it,
+            "setup_s": round(t_setup, 1),
             "sample": "oracle GMG-PCG with explicit SciPy level matrices (same chain, Chebyshev "
                       "degree, tolerance and right-hand side), one thread"}
 
@@ -313,15 +460,111 @@ def matrix_based(mf, op, x, t_mf_ms, spec, max_bytes=40e9):
     return out
 
 
+def _timed(fn, reps):
+    """Mean milliseconds per call of fn over `reps` back-to-back calls, from HIP
+    events on the current stream (three untimed calls first)."""
+    import torch
+    for _ in range(3):
+        fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def oracle_certificate(spec, f, u, rows):
+    """The error of a GPU solution against the FP64 oracle where the oracle
+    cannot solve: b - A x on sampled rows with the oracle's element matrices,
+    relative to max|b| (the solve stopped at ||b - A x|| <= 1e-10 ||b||)."""
+    import numpy as np
+    from oracle import operator as oop
+    uh = u.detach().cpu().numpy()
+    fh = f[rows].cpu().numpy() if hasattr(f, "cpu") else f[rows]
+    r = fh - oop.apply_rows(spec, lambda g: uh[np.asarray(g)], rows)
+    return float(np.abs(r).max() / np.abs(f.cpu().numpy()).max())
+
+
+def measure_point(mf, spec, chain, degree, R, solves=3, cert_rows=8):
+    """The metric at one configuration: FP64 and FP32 kernel times (y += A x,
+    HIP events), y = A x through the binding, PCG to 1e-10 from zero in FP64 and
+    mixed precision (median of `solves` after one untimed solve each), their
+    iterations, true residuals, byte models and HBM fractions, and the
+    oracle's sampled-row residual of both solutions."""
+    import numpy as np
+    import torch
+    import synth
+    N = spec.n_dof
+    t0 = time.perf_counter()
+    ops, mg32 = mf.hierarchy(spec, coarsening=chain, degree=degree, precision=torch.float32)
+    op = ops[0]
+    mg64 = mf.Multigrid(ops, mg32.transfers, degree=degree, precision=torch.float64)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    g = torch.arange(N, device="cuda", dtype=torch.float64)
+    x = torch.sin(0.37 * g)
+    y = torch.zeros_like(x)
+    x32, y32 = x.float(), torch.zeros(N, device="cuda", dtype=torch.float32)
+    t_apply = _timed(lambda: op.apply(x, out=y), R)
+    t_k64 = _timed(lambda: op.apply_add(x, y), R)
+    t_k32 = _timed(lambda: op.apply_add(x32, y32), R)
+    f = torch.as_tensor(synth.uniform(2, N), device="cuda")
+    res = {}
+    for tag, mg in (("fp64", mg64), ("mixed", mg32)):
+        u, info = mf.pcg(op, f, mg=mg, rtol=1e-10, max_it=200)
+        ts = []
+        for _ in range(solves):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            u, info = mf.pcg(op, f, mg=mg, rtol=1e-10, max_it=200)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - a) * 1e3)
+        ms = _median(ts)
+        rr = float(torch.linalg.norm(f - op.apply(u)) / torch.linalg.norm(f))
+        res[tag] = (u, ms, info.iters[0], rr)
+    rng = np.random.default_rng(11)
+    rows = np.concatenate([rng.integers(0, N, cert_rows), [0, N - 1]])
+    u64, u32 = res["fp64"][0], res["mixed"][0]
+    kname, _, _ = apply_kernel(spec)
+    b64 = algorithmic_bytes(spec, spec.n_elem, N, 8, spec.quad)
+    b32 = algorithmic_bytes(spec, spec.n_elem, N, 4, spec.quad)
+    out = {"n_dof": N, "n_elem": spec.n_elem, "elements": list(spec.n), "p": spec.p,
+           "quadrature": spec.quad, "nq1d": spec.q, "multigrid": chain_str(spec.p, chain),
+           "kernel": kname, "setup_s": round(setup, 2),
+           "fp64_apply_ms": round(t_apply, 4), "fp64_apply_gdofs": round(N / t_apply / 1e6, 2),
+           "fp64_kernel_ms": round(t_k64, 4), "fp64_kernel_gdofs": round(N / t_k64 / 1e6, 2),
+           "fp64_kernel_hbm_frac": round(b64 / (t_k64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "fp32_kernel_ms": round(t_k32, 4), "fp32_kernel_gdofs": round(N / t_k32 / 1e6, 2),
+           "fp32_kernel_hbm_frac": round(b32 / (t_k32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    for tag in ("fp64", "mixed"):
+        _, ms, it, rr = res[tag]
+        out[f"pcg_{tag}"] = {"ms": round(ms, 3), "iters": it, "ms_per_iteration": round(ms / it, 3),
+                             "true_rel_residual": rr,
+                             "roofline": pcg_roofline(spec, chain, degree, ms, it, tag == "mixed"),
+                             "oracle_rows_residual_rel": oracle_certificate(spec, f, res[tag][0],
+                                                                            rows)}
+    out["mixed_vs_fp64_rel_l2"] = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+    out["oracle_certificate"] = (f"b - A x on {len(rows)} sampled rows with the oracle's element "
+                                 f"matrices, max over the rows / max|b|")
+    del ops, mg32, mg64, op, res, u64, u32, x, y, x32, y32, f
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="slab-p4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pcg", action="store_true")
-    ap.add_argument("--apply-reps", type=int, default=100)
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the p = 2..7 sweep, c3 Gauss and c2 sections of the default run")
+    ap.add_argument("--apply-reps", type=int, default=None,
+                    help="applies per step (default 20 above 4M DOFs, else 100)")
     ap.add_argument("--coarsening", default=None,
                     help="multigrid chain below the finest level, e.g. p5,p3,p1 or p2,p1,h "
                          "(default: the workload's)")
@@ -333,8 +576,8 @@ def main():
                     help="also run an elementwise copy of 2 x N doubles (HBM counter reference)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has "
-              f"no multi-GPU path in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library has "
+              f"no multi-GPU path, and this build runs on one GPU", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -347,6 +590,7 @@ def main():
     kind = {"c4": "grad", "c5": "monodomain", "c5-bdf2": "monodomain"}.get(args.workload, "pcg")
     if args.no_pcg and kind == "pcg":
         kind = None
+    sweep = args.workload == "slab-p4" and not args.no_sweep and kind == "pcg"
     log(f"workload {args.workload}: {desc}; N = {spec.n_dof:,} DOFs, {spec.n_elem:,} elements")
     dev = "cuda"
     t0 = time.perf_counter()
@@ -356,7 +600,6 @@ def main():
     if args.cheb_degree:
         cheb_degree = args.cheb_degree
     B = 1
-    extra = None
     if kind == "pcg":
         ops, mg32 = mf.hierarchy(spec, coarsening=coarsening, degree=cheb_degree,
                                  precision=torch.float32)
@@ -401,7 +644,7 @@ def main():
     y32 = torch.empty_like(x32)
     opf = op if kind != "grad" else op32
     E = lambda: torch.cuda.Event(enable_timing=True)
-    R = args.apply_reps
+    R = args.apply_reps or (20 if N > SMALL_DOFS else 100)
 
     def step(rec):
         ev = [E() for _ in range(10)]
@@ -451,6 +694,7 @@ def main():
     for _ in range(args.warmup):
         step(warm)
     torch.cuda.synchronize()
+    log(f"warm-up done ({args.warmup} steps); timing {args.steps} steps")
     rec = {}
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -458,6 +702,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall / args.steps * 1e3
+    log(f"timed steps done: {ms_step:.1f} ms per step")
 
     def mean_ms(a, b):
         return sum(ev[a].elapsed_time(ev[b]) for ev in rec["ev"]) / len(rec["ev"])
@@ -472,6 +717,7 @@ def main():
     flops = B * algorithmic_flops(spec, spec.n_elem, N, spec.quad)
     achieved = bytes64 / (t_kernel * 1e-3) / 1e9
     kname, ksrc, kmodel = apply_kernel(spec)
+    traffic, traffic_src = measured_traffic(kname, ksrc, args.workload)
     out = {
         "metric": "operator-apply GDOF/s and PCG time-to-1e-10, FP64 vs mixed, p=2..7",
         "value": round(gdofs, 4),
@@ -500,7 +746,7 @@ def main():
                   "fp64_tflops": round(flops / (t_kernel * 1e-3) / 1e12, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(kname, ksrc, args.workload),
+                     "traffic": traffic, "traffic_source": traffic_src,
                      "kernel": kname,
                      "bytes_per_launch": int(bytes64),
                      "bytes_model": kmodel},
@@ -524,6 +770,12 @@ def main():
                       "mixed_vs_fp64_rel_l2": rel_mixed,
                       "lambda_max_per_level": [round(v, 5) for v in lam64],
                       "tol": 1e-10, "x0": "zero", "setup_s": round(t_setup, 3)}
+        out["pcg_roofline"] = {
+            "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "fp64": pcg_roofline(spec, coarsening, cheb_degree, t64, it64, False),
+            "mixed": pcg_roofline(spec, coarsening, cheb_degree, t32, it32, True),
+            "model": "algorithmic bytes of every kernel of the solve (pcg_bytes_model) / "
+                     "measured solve time (HIP events)"}
     elif kind == "grad":
         g, g32 = rec["grad"], rec["grad32"]
         out["grad"] = {"batch": B, "forward_solve_ms": round(mean_ms(5, 6), 4),
@@ -547,11 +799,11 @@ def main():
                              "V_range_mV": [round(float(sim.V.min()), 3), round(float(sim.V.max()), 3)],
                              "sim_time_ms": round(sim.t, 4), "setup_s": round(t_setup, 3),
                              "scheme": sim.scheme}
-        if sim.scheme == "bdf2":
-            act = sim.act[sim.act >= 0]
-            out["monodomain"]["activated_fraction"] = round(act.numel() / sim.act.numel(), 5)
-            out["monodomain"]["activation_ms_range"] = (
-                [round(float(act.min()), 4), round(float(act.max()), 4)] if act.numel() else None)
+        act = sim.act[sim.act >= 0]
+        out["monodomain"]["activated_fraction"] = round(act.numel() / sim.act.numel(), 5)
+        out["monodomain"]["activation_ms_range"] = (
+            [round(float(act.min()), 4), round(float(act.max()), 4)] if act.numel() else None)
+        out["monodomain"]["activation"] = "time of the largest |dV/dt| per node (step midpoint)"
     if kind == "pcg" and not args.no_matrix_based:
         out["matrix_based"] = matrix_based(mf, op, x, t_kernel, spec)
     if args.copy_ref:
@@ -561,13 +813,32 @@ def main():
             torch.add(x, 0.0, out=y)
         torch.cuda.synchronize()
         out["copy_ref_bytes"] = {"read": 8 * NB, "write": 8 * NB}
+    if sweep:
+        # free the main workload before the sweep builds its own hierarchies
+        del ops, mg32, mg64, op, opf, rec, warm, x, y, x32, y32, f
+        torch.cuda.empty_cache()
+        out["sweep"] = {}
+        for p in (2, 3, 4, 5, 6, 7):
+            sp = synth.sweep(p)
+            log(f"sweep p={p}: {sp.n_dof:,} DOFs ...")
+            pt = measure_point(mf, sp, coarsening_for(p, sp.n_dof), 3, 20)
+            out["sweep"][f"p{p}"] = pt
+            log(f"  p={p}: FP64 kernel {pt['fp64_kernel_ms']} ms, PCG {pt['pcg_fp64']['ms']} / "
+                f"{pt['pcg_mixed']['ms']} ms")
+        sp = synth.C3_SEM
+        log(f"c3 Gauss q=9: {sp.n_dof:,} DOFs ...")
+        out["c3_gauss"] = measure_point(mf, sp, coarsening_for(7, sp.n_dof), 3, 20)
+        out["c3_gauss"]["workload"] = workload("c3-gauss")[1]
+        log("c2 ...")
+        out["c2"] = measure_point(mf, synth.C2, coarsening_for(4, synth.C2.n_dof), 3, 100,
+                                  solves=5)
+        out["c2"]["workload"] = workload("c2")[1]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(spec)
-        if kind == "pcg":
-            pcg_cpu = cpu_pcg_baseline(spec, coarsening, cheb_degree)
-            if pcg_cpu is not None:
-                out["cpu_baseline"]["pcg"] = pcg_cpu
+        pcg_cpu = cpu_pcg_baseline(synth.C2, coarsening_for(4, synth.C2.n_dof), 3)
+        if pcg_cpu is not None:
+            out["cpu_baseline"]["c2_pcg"] = pcg_cpu
     print(json.dumps(out), flush=True)
 
 

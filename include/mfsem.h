@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MFSEM_ABI_VERSION 4
+#define MFSEM_ABI_VERSION 5
 #define MFSEM_MAX_P 8
 
 typedef enum {
@@ -353,16 +353,32 @@ mfsem_status mfsem_ap_imex_rhs(int64_t n, double dt, double chi, double cm,
  *   b = mass_diag * (chi*cm/dt * (4 V^n - V^{n-1})/2
  *                    + chi*cm*(v_amp/t_scale) * F(u*, w^{n+1}) + i_stim),
  * the right-hand side of (3/2 chi*cm/dt M + K) V^{n+1} = b; then
- * w_old <- w^n and w <- w^{n+1}.  V = V^n (at time t), V_old = V^{n-1}.
- * act (may be NULL): where act < 0 and V_old < v_act <= V, act is set to the
- * crossing time interpolated linearly in [t - dt, t] (activation times).
+ * w_old <- w^n and w <- w^{n+1}.  V = V^n, V_old = V^{n-1}.
  * All arrays [device][n] FP64; i_stim may be NULL (zero).  A first step from
  * rest may take V_old = V and w_old = w.                                     */
 mfsem_status mfsem_ap_bdf2_rhs(int64_t n, double dt, double chi, double cm,
                                const mfsem_ap_params* prm, const double* V, const double* V_old,
                                double* w, double* w_old, const double* i_stim,
-                               const double* mass_diag, double* b, double t, double v_act,
-                               double* act, void* stream);
+                               const double* mass_diag, double* b, void* stream);
+
+/* Activation times (Section 5.1: at each node, the time at which the
+ * transmembrane potential changes fastest, tau = argmax_t |du/dt|), kept as a
+ * running maximum over a time loop.  Call once after every step with
+ * V = V^{n+1} (at time t) and V_old = V^n (at t - dt):
+ *   q = |V - V_old| / dt;   where q > rate:  rate = q,  act = t - dt/2
+ * (the step's midpoint, where the difference quotient estimates du/dt to
+ * second order; the comparison is strict, so of equally steep steps the
+ * earliest is kept).  Start from act = -1 and rate = 0: nodes whose potential
+ * never changes keep -1.  act and rate must both be given or both be NULL.
+ * cross (may be NULL): where cross < 0 and V_old < v_cross <= V, cross is set
+ * to the crossing time interpolated linearly in [t - dt, t] (a level
+ * crossing, which precedes the steepest point of an upstroke; not the
+ * activation time).  At least one of act and cross is given.
+ * All arrays [device][n] FP64; V, V_old are read only.  EINVAL for dt <= 0,
+ * non-finite t or v_cross, or a NULL array with n > 0.                      */
+mfsem_status mfsem_activation_update(int64_t n, double t, double dt, const double* V,
+                                     const double* V_old, double* act, double* rate,
+                                     double v_cross, double* cross, void* stream);
 
 /* out = 2 v - v_old: the linear extrapolation of a time series (the V* of
  * the BDF2 scheme, Section 3), used as the initial guess of the next implicit

@@ -100,27 +100,27 @@ def activation_times(V_series, t_series):
     rate = np.zeros(n_dof)
     for i in range(n_dof):
         for n in range(len(t) - 1):
-            r = abs(V[n + 1, i] - V[n, i]) / (t[n + 1] - t[n])
+            dt = t[n + 1] - t[n]
+            r = abs(V[n + 1, i] - V[n, i]) / dt
             if r > rate[i]:
                 rate[i] = r
-                tau[i] = t[n] + 0.5 * (t[n + 1] - t[n])
+                tau[i] = t[n + 1] - 0.5 * dt
     return tau, rate
 
 
-def activation_update(act, rate, V_old, V, t_old, t_new):
+def activation_update(act, rate, V_old, V, t, dt):
     """The same definition kept as a running maximum, one step at a time (the
-    form a time loop can afford): where |V - V_old| / (t_new - t_old) exceeds
-    rate, rate takes it and act the step's midpoint.  Start from act = -1 and
-    rate = 0; after the last step act equals activation_times over the series.
-    Returns new (act, rate)."""
+    form a time loop can afford), for a step from V_old at t - dt to V at t:
+    where |V - V_old| / dt exceeds rate, rate takes it and act the step's
+    midpoint t - dt/2.  Start from act = -1 and rate = 0; after the last step
+    act equals activation_times over the series.  Returns new (act, rate)."""
     act = np.array(act, dtype=np.float64, copy=True)
     rate = np.array(rate, dtype=np.float64, copy=True)
-    dt = t_new - t_old
     for i in range(len(act)):
         r = abs(V[i] - V_old[i]) / dt
         if r > rate[i]:
             rate[i] = r
-            act[i] = t_old + 0.5 * dt
+            act[i] = t - 0.5 * dt
     return act, rate
 
 

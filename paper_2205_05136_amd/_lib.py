@@ -104,8 +104,9 @@ PROTOTYPES = {
     "mfsem_ap_imex_rhs": (_ST, [C.c_int64, C.c_double, C.c_double, C.c_double,
                                 C.POINTER(APParams), _P, _P, _P, _P, _P, _P]),
     "mfsem_ap_bdf2_rhs": (_ST, [C.c_int64, C.c_double, C.c_double, C.c_double,
-                                C.POINTER(APParams), _P, _P, _P, _P, _P, _P, _P, C.c_double,
-                                C.c_double, _P, _P]),
+                                C.POINTER(APParams), _P, _P, _P, _P, _P, _P, _P, _P]),
+    "mfsem_activation_update": (_ST, [C.c_int64, C.c_double, C.c_double, _P, _P, _P, _P,
+                                      C.c_double, _P, _P]),
 }
 
 _lib = None

@@ -462,17 +462,26 @@ def ap_imex_rhs(V, w, mass_diag, dt, chi, cm, params: dict, i_stim=None, out=Non
 
 
 def ap_bdf2_rhs(V, V_old, w, w_old, mass_diag, dt, chi, cm, params: dict, i_stim=None,
-                out=None, t=0.0, v_act=0.0, act=None):
-    """b of the BDF2 step; w_old <- w, w <- w^{n+1}; activation times in `act`
-    (mfsem_ap_bdf2_rhs)."""
+                out=None):
+    """b of the BDF2 step; w_old <- w, w <- w^{n+1} (mfsem_ap_bdf2_rhs)."""
     b = torch.empty_like(V) if out is None else out
-    _pointwise(V.numel(), V.device, V, V_old, w, w_old, mass_diag, i_stim, b, act)
+    _pointwise(V.numel(), V.device, V, V_old, w, w_old, mass_diag, i_stim, b)
     prm = _ap_params(params)
     L.check(L.load().mfsem_ap_bdf2_rhs(V.numel(), dt, chi, cm, C.byref(prm), _ptr(V),
                                        _ptr(V_old), _ptr(w), _ptr(w_old), _ptr(i_stim),
-                                       _ptr(mass_diag), _ptr(b), float(t), float(v_act),
-                                       _ptr(act), _stream()))
+                                       _ptr(mass_diag), _ptr(b), _stream()))
     return b
+
+
+def activation_update(V, V_old, t, dt, act=None, rate=None, v_cross=0.0, cross=None):
+    """Running activation times after a step from V_old (at t - dt) to V (at t):
+    act, rate take the step's midpoint and |dV/dt| where it is the steepest
+    so far; cross records the first upward crossing of v_cross
+    (mfsem_activation_update).  Updated in place."""
+    _pointwise(V.numel(), V.device, V, V_old, act, rate, cross)
+    L.check(L.load().mfsem_activation_update(V.numel(), float(t), float(dt), _ptr(V),
+                                             _ptr(V_old), _ptr(act), _ptr(rate), float(v_cross),
+                                             _ptr(cross), _stream()))
 
 
 def extrapolate(v, v_old, out=None):

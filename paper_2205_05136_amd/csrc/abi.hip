@@ -30,8 +30,9 @@ void launch_ap(int64_t n, double dt, double chi, double cm, const mfsem_ap_param
                hipStream_t s);
 void launch_ap_bdf2(int64_t n, double dt, double chi, double cm, const mfsem_ap_params& prm,
                     const double* V, const double* Vo, double* w, double* wo, const double* istim,
-                    const double* m, double* b, double t, double v_act, double* act,
-                    hipStream_t s);
+                    const double* m, double* b, hipStream_t s);
+void launch_activation(int64_t n, double t, double dt, const double* V, const double* Vo,
+                       double* act, double* rate, double v_cross, double* cross, hipStream_t s);
 void launch_extrapolate(int64_t n, const double* v, const double* vo, double* out, hipStream_t s);
 
 namespace {
@@ -561,17 +562,30 @@ mfsem_status mfsem_ap_imex_rhs(int64_t n, double dt, double chi, double cm,
 mfsem_status mfsem_ap_bdf2_rhs(int64_t n, double dt, double chi, double cm,
                                const mfsem_ap_params* prm, const double* V, const double* V_old,
                                double* w, double* w_old, const double* i_stim,
-                               const double* mass_diag, double* b, double t, double v_act,
-                               double* act, void* stream) {
+                               const double* mass_diag, double* b, void* stream) {
   return guarded([&] {
     require(n >= 0, "n must be >= 0");
     require(dt > 0.0 && chi > 0.0 && cm > 0.0, "dt, chi and cm must be positive");
     require(prm != nullptr, "params is NULL");
     require(prm->v_amp != 0.0 && prm->t_scale > 0.0, "v_amp != 0 and t_scale > 0 required");
     require(n == 0 || (V && V_old && w && w_old && mass_diag && b), "NULL array");
-    require(std::isfinite(t) && std::isfinite(v_act), "t and v_act must be finite");
-    launch_ap_bdf2(n, dt, chi, cm, *prm, V, V_old, w, w_old, i_stim, mass_diag, b, t, v_act, act,
+    launch_ap_bdf2(n, dt, chi, cm, *prm, V, V_old, w, w_old, i_stim, mass_diag, b,
                    as_stream(stream));
+  });
+}
+
+mfsem_status mfsem_activation_update(int64_t n, double t, double dt, const double* V,
+                                     const double* V_old, double* act, double* rate,
+                                     double v_cross, double* cross, void* stream) {
+  return guarded([&] {
+    require(n >= 0, "n must be >= 0");
+    require(dt > 0.0 && std::isfinite(dt), "dt must be positive and finite");
+    require(std::isfinite(t), "t must be finite");
+    require((act == nullptr) == (rate == nullptr), "act and rate must both be given or both NULL");
+    require(act != nullptr || cross != nullptr, "nothing to update (act, rate and cross are NULL)");
+    require(cross == nullptr || std::isfinite(v_cross), "v_cross must be finite");
+    require(n == 0 || (V && V_old), "NULL array");
+    launch_activation(n, t, dt, V, V_old, act, rate, v_cross, cross, as_stream(stream));
   });
 }
 

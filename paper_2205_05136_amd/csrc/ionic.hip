@@ -40,15 +40,12 @@ __global__ void ap_kernel(int64_t n, double dt, double chi, double cm, mfsem_ap_
 //            h r w^2 + (3 + h (eps0 + r c)) w + (h eps0 c - 4 w^n + w^{n-1}) = 0,
 //            solved by the root that tends to the linear solution as r -> 0;
 //   b = m (chi cm/dt (4 V^n - V^{n-1})/2 + chi cm (v_amp/t_scale) F(u*, w^{n+1}) + I_stim),
-// then w^{n-1} <- w^n, w^n <- w^{n+1}.  With act != NULL, the first upward
-// crossing of v_act between V^{n-1} (at t - dt) and V^n (at t) is recorded by
-// linear interpolation where act < 0.
+// then w^{n-1} <- w^n, w^n <- w^{n+1}.
 __global__ void ap_bdf2_kernel(int64_t n, double dt, double chi, double cm, mfsem_ap_params prm,
                                const double* __restrict__ V, const double* __restrict__ Vo,
                                double* __restrict__ w, double* __restrict__ wo,
                                const double* __restrict__ istim, const double* __restrict__ m,
-                               double* __restrict__ b, double t, double v_act,
-                               double* __restrict__ act) {
+                               double* __restrict__ b) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const double a1 = chi * cm / dt;
   const double fscale = chi * cm * (prm.v_amp / prm.t_scale);
@@ -68,8 +65,35 @@ __global__ void ap_bdf2_kernel(int64_t n, double dt, double chi, double cm, mfse
     b[i] = m[i] * (a1 * 0.5 * (4.0 * v - vo) + fscale * F + is);
     wo[i] = wn;
     w[i] = wnew;
-    if (act && act[i] < 0.0 && vo < v_act && v >= v_act)
-      act[i] = (t - dt) + dt * (v_act - vo) / (v - vo);
+  }
+}
+
+// Activation times (Section 5.1: the instant of the largest |du/dt| at each
+// node) as a running maximum over the time loop.  V = V^{n+1} at time t and
+// Vo = V^n at t - dt; the difference quotient |V - Vo|/dt estimates |du/dt| at
+// the step's midpoint, so a step steeper than every earlier one (strictly:
+// ties keep the earlier step) sets rate to it and act to t - dt/2.  With
+// cross != NULL the first upward crossing of v_cross, interpolated linearly in
+// [t - dt, t], is kept as well (a level crossing, not the activation time).
+// One pass, 16 B read per node and 16-24 B read and (rarely) written.
+template <bool CROSS>
+__global__ void activation_kernel(int64_t n, double t, double dt, const double* __restrict__ V,
+                                  const double* __restrict__ Vo, double* __restrict__ act,
+                                  double* __restrict__ rate, double v_cross,
+                                  double* __restrict__ cross) {
+  const double t_mid = t - 0.5 * dt;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = V[i], vo = Vo[i];
+    if (act) {
+      const double q = fabs(v - vo) / dt;
+      if (q > rate[i]) {
+        rate[i] = q;
+        act[i] = t_mid;
+      }
+    }
+    if (CROSS && cross[i] < 0.0 && vo < v_cross && v >= v_cross)
+      cross[i] = (t - dt) + dt * (v_cross - vo) / (v - vo);
   }
 }
 
@@ -91,14 +115,26 @@ void launch_extrapolate(int64_t n, const double* v, const double* vo, double* ou
 
 void launch_ap_bdf2(int64_t n, double dt, double chi, double cm, const mfsem_ap_params& prm,
                     const double* V, const double* Vo, double* w, double* wo, const double* istim,
-                    const double* m, double* b, double t, double v_act, double* act,
-                    hipStream_t s) {
+                    const double* m, double* b, hipStream_t s) {
   if (n <= 0) return;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  ap_bdf2_kernel<<<(unsigned)blocks, 256, 0, s>>>(n, dt, chi, cm, prm, V, Vo, w, wo, istim, m, b,
-                                                  t, v_act, act);
+  ap_bdf2_kernel<<<(unsigned)blocks, 256, 0, s>>>(n, dt, chi, cm, prm, V, Vo, w, wo, istim, m, b);
   MFSEM_LAUNCH("ap_bdf2_kernel");
+}
+
+void launch_activation(int64_t n, double t, double dt, const double* V, const double* Vo,
+                       double* act, double* rate, double v_cross, double* cross, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (cross)
+    activation_kernel<true><<<(unsigned)blocks, 256, 0, s>>>(n, t, dt, V, Vo, act, rate, v_cross,
+                                                             cross);
+  else
+    activation_kernel<false><<<(unsigned)blocks, 256, 0, s>>>(n, t, dt, V, Vo, act, rate, v_cross,
+                                                              cross);
+  MFSEM_LAUNCH("activation_kernel");
 }
 
 void launch_ap(int64_t n, double dt, double chi, double cm, const mfsem_ap_params& prm,

@@ -53,3 +53,38 @@ def test_byte_model_at_p4():
     b = bench.algorithmic_bytes(spec, spec.n_elem, spec.n_dof, 8, "gll")
     assert b == 24 * spec.n_dof + 48 * spec.n_elem * 125 + 8 * spec.n_elem
     assert 116 < b / spec.n_dof < 118
+
+
+def test_pcg_byte_model_counts_every_kernel():
+    """The solve's byte model at p = 4 (chain 4 -> 2 -> 1, Chebyshev degree 3,
+    coarsest degree 6): the V-cycle runs 2k applies on each level above the
+    coarsest and coarse_degree - 1 on the coarsest, 2k smoother steps per level
+    (one from zero), and the CG adds one FP64 apply and 112 B/DOF of vector
+    traffic (r.z 16, p update 24, p.q 16, x/r update 56); the mixed V-cycle
+    moves half the V-cycle bytes."""
+    spec = synth.sweep(4)
+    chain = bench.coarsening_for(4, spec.n_dof)
+    m64 = bench.pcg_bytes_model(spec, chain, 3, 6, False)
+    m32 = bench.pcg_bytes_model(spec, chain, 3, 6, True)
+    A = [bench.apply_bytes(p, spec.n, p + 1, "gll", 8) for p in (4, 2, 1)]
+    assert m64["parts"]["vcycle_apply"] == 6 * A[0] + 6 * A[1] + 5 * A[2]
+    assert m64["parts"]["cg_apply_fp64"] == bench.algorithmic_bytes(spec, spec.n_elem,
+                                                                    spec.n_dof, 8, "gll")
+    assert m64["parts"]["cg_vectors"] == 112 * spec.n_dof
+    N = [bench.math.prod(bench._nodes(p, spec.n)) for p in (4, 2, 1)]
+    # per level: 3 words from zero + 5 steps of 6 words, + 1 word clearing b below the finest
+    assert m64["parts"]["vcycle_smoother"] == 8 * (33 * N[0] + 34 * N[1] + (3 + 5 * 6 + 1) * N[2])
+    for k in ("vcycle_apply", "vcycle_smoother", "restriction", "prolongation"):
+        assert 2 * m32["parts"][k] == m64["parts"][k]
+    assert m64["iteration"] == sum(m64["parts"].values())
+    # about 75 GB per FP64 iteration on the 51M-DOF slab
+    assert 70e9 < m64["iteration"] < 80e9 and 40e9 < m32["iteration"] < 47e9
+
+
+def test_level_plan_follows_the_chain():
+    spec = synth.paper_slab(4)
+    lv = bench.level_plan(spec, (("p", 2), ("p", 1), ("h",), ("h",)))
+    assert [l[0] for l in lv] == [4, 2, 1, 1, 1]
+    assert lv[-1][1] == (19, 6, 3) and all(l[3] == "gll" for l in lv)
+    g = bench.level_plan(synth.C3_SEM, (("p", 5),))
+    assert g[0][2:] == (9, "gauss") and g[1][2:] == (6, "gll")

@@ -803,11 +803,11 @@ def test_activation_running_form_equals_series_form_and_brute_force():
     tau, rate = ionic.activation_times(V, t)
     act, r = np.full(n, -1.0), np.zeros(n)
     for k in range(n_steps):
-        act, r = ionic.activation_update(act, r, V[k], V[k + 1], t[k], t[k + 1])
+        act, r = ionic.activation_update(act, r, V[k], V[k + 1], t[k + 1], t[k + 1] - t[k])
     assert np.array_equal(act, tau) and np.array_equal(r, rate)
     q = np.abs(np.diff(V, axis=0)) / np.diff(t)[:, None]
     k = np.argmax(q, axis=0)
-    mid = 0.5 * (t[:-1] + t[1:])
+    mid = t[1:] - 0.5 * np.diff(t)
     moved = q.max(axis=0) > 0
     np.testing.assert_allclose(tau[moved], mid[k[moved]], rtol=0, atol=1e-15)
     assert np.all(tau[~moved] == -1.0)
