@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MFSEM_ABI_VERSION 5
+#define MFSEM_ABI_VERSION 6
 #define MFSEM_MAX_P 8
 
 typedef enum {
@@ -325,6 +325,26 @@ mfsem_status mfsem_pcg_workspace_bytes(const mfsem_op* op, const mfsem_mg* mg, s
 mfsem_status mfsem_pcg(const mfsem_op* op, const mfsem_mg* mg, const double* b, double* x,
                        const mfsem_solve_opts* opts, mfsem_solve_info* info, void* ws,
                        size_t ws_bytes, void* stream);
+
+/* The same solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * instead of a caller workspace, the CG work vectors, scalars and reduction
+ * partials live in a fixed array of MFSEM_NOALLOC_SCRATCH_MB MiB that the
+ * library holds on every GPU it runs on until the process ends.  Nothing is
+ * allocated or freed by this call (no hipMalloc, hipFree or allocating
+ * library routine).  The scratch serves n_dof * batch up to about 1.3M DOFs
+ * (the size mfsem_pcg_workspace_bytes reports must not exceed it): larger
+ * solves fail with EINVAL before any launch, and the message says so.
+ * The array of the calling thread's current device is used (it must be the
+ * device of op, mg and stream).  Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents (each call writes every value
+ * before reading it, so nothing needs to start at zero): calls that overlap
+ * on one GPU (from several host threads or streams) race and must be
+ * serialised by the caller.  Arguments and results as mfsem_pcg.  [sync]    */
+#define MFSEM_NOALLOC_SCRATCH_MB 64
+mfsem_status mfsem_pcg_noalloc(const mfsem_op* op, const mfsem_mg* mg, const double* b,
+                               double* x, const mfsem_solve_opts* opts, mfsem_solve_info* info,
+                               void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Pointwise ionic step for the full monodomain time loop (the DOF-wise ionic

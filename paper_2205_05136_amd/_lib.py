@@ -18,6 +18,7 @@ MFSEM_F64, MFSEM_F32 = 0, 1
 MFSEM_TRANSFER_P, MFSEM_TRANSFER_H = 0, 1
 MFSEM_GEOM_AUTO, MFSEM_GEOM_STORED, MFSEM_GEOM_ONTHEFLY = 0, 1, 2
 MAX_P = 8
+NOALLOC_SCRATCH_MB = 64   # MFSEM_NOALLOC_SCRATCH_MB: the fixed scratch of mfsem_pcg_noalloc
 
 
 class MfsemError(RuntimeError):
@@ -101,6 +102,7 @@ PROTOTYPES = {
     "mfsem_pcg_workspace_bytes": (_ST, [_P, _P, C.POINTER(C.c_size_t)]),
     "mfsem_pcg": (_ST, [_P, _P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P,
                         C.c_size_t, _P]),
+    "mfsem_pcg_noalloc": (_ST, [_P, _P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
     "mfsem_ap_imex_rhs": (_ST, [C.c_int64, C.c_double, C.c_double, C.c_double,
                                 C.POINTER(APParams), _P, _P, _P, _P, _P, _P]),
     "mfsem_ap_bdf2_rhs": (_ST, [C.c_int64, C.c_double, C.c_double, C.c_double,

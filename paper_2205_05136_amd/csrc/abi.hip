@@ -3,6 +3,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "solver.hpp"
@@ -21,6 +22,36 @@ void check_hip(hipError_t e, const char* what) {
   if (e != hipSuccess)
     fail(MFSEM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+namespace {
+// Fixed device memory of mfsem_pcg_noalloc: the PCG work vectors, per-member
+// scalars and reduction partials for callers that cannot allocate.  Every GPU
+// the library runs on holds its own copy for the life of the process.  Host
+// code never uses the array's name as an address (on the host it is a
+// stand-in symbol): it takes each device's address from hipGetSymbolAddress,
+// once per device, with that device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)MFSEM_NOALLOC_SCRATCH_MB << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the scratch array on the calling thread's current device.
+void* noalloc_scratch() {
+  int dev = -1;
+  check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    fail(MFSEM_EDEVICE, "device index " + std::to_string(dev) + " beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (ptr == nullptr) fail(MFSEM_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
 
 void launch_box(const mfsem_box_desc& d, int64_t n_elem, int64_t n_dof, const double* xi_host,
                 int32_t* ed, double* xyz, double* fib, hipStream_t s);
@@ -517,15 +548,19 @@ mfsem_status mfsem_pcg_workspace_bytes(const mfsem_op* op, const mfsem_mg* mg, s
   });
 }
 
-mfsem_status mfsem_pcg(const mfsem_op* op, const mfsem_mg* mg, const double* b, double* x,
+}  // extern "C"
+
+namespace {
+// (P)CG entry shared by mfsem_pcg and mfsem_pcg_noalloc: validation, then the
+// solve in the workspace `ws` of ws_bytes (the caller's, or the scratch array).
+mfsem_status pcg_entry(const mfsem_op* op, const mfsem_mg* mg, const double* b, double* x,
                        const mfsem_solve_opts* opts, mfsem_solve_info* info, void* ws,
-                       size_t ws_bytes, void* stream) {
+                       size_t ws_bytes, bool noalloc, void* stream) {
   mfsem_status solve_status = MFSEM_OK;
   mfsem_status st = guarded([&] {
     check_op(op, MFSEM_F64);
-    require(b && x && opts && info && ws, "NULL argument");
+    require(b && x && opts && info && (ws || noalloc), "NULL argument");
     require(b != x, "b and x must not alias");
-    require_aligned(ws, 256, "workspace");
     require(opts->max_it >= 1, "max_it must be >= 1");
     require(opts->rtol >= 0.0 && opts->atol >= 0.0 && (opts->rtol > 0.0 || opts->atol > 0.0),
             "need rtol > 0 or atol > 0");
@@ -533,7 +568,18 @@ mfsem_status mfsem_pcg(const mfsem_op* op, const mfsem_mg* mg, const double* b, 
       require(mg->lv[0].op->d.n_dof == op->d.n_dof && mg->batch == op->d.batch,
               "multigrid finest level does not match the operator");
     }
-    require(ws_bytes >= pcg_bytes(*op, mg), "workspace too small");
+    const size_t need = pcg_bytes(*op, mg);
+    if (noalloc) {
+      if (need > ws_bytes)
+        fail(MFSEM_EINVAL, "mfsem_pcg_noalloc: the solve needs " + std::to_string(need) +
+                               " bytes of work space, more than the library's fixed " +
+                               std::to_string(ws_bytes >> 20) +
+                               " MiB scratch (n_dof * batch too large); use mfsem_pcg");
+      ws = noalloc_scratch();
+    } else {
+      require_aligned(ws, 256, "workspace");
+      require(ws_bytes >= need, "workspace too small");
+    }
     solve_status = pcg_solve(*op, mg, b, x, *opts, info, ws, ws_bytes, as_stream(stream));
     if (solve_status != MFSEM_OK) {
       std::string m = "PCG did not converge for every batch member (worst status " +
@@ -542,6 +588,21 @@ mfsem_status mfsem_pcg(const mfsem_op* op, const mfsem_mg* mg, const double* b, 
     }
   });
   return st != MFSEM_OK ? st : solve_status;
+}
+}  // namespace
+
+extern "C" {
+
+mfsem_status mfsem_pcg(const mfsem_op* op, const mfsem_mg* mg, const double* b, double* x,
+                       const mfsem_solve_opts* opts, mfsem_solve_info* info, void* ws,
+                       size_t ws_bytes, void* stream) {
+  return pcg_entry(op, mg, b, x, opts, info, ws, ws_bytes, false, stream);
+}
+
+mfsem_status mfsem_pcg_noalloc(const mfsem_op* op, const mfsem_mg* mg, const double* b,
+                               double* x, const mfsem_solve_opts* opts, mfsem_solve_info* info,
+                               void* stream) {
+  return pcg_entry(op, mg, b, x, opts, info, nullptr, NOALLOC_SCRATCH_BYTES, true, stream);
 }
 
 // ----------------------------------------------------------------- ionic ---
