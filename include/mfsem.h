@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MFSEM_ABI_VERSION 6
+#define MFSEM_ABI_VERSION 8
 #define MFSEM_MAX_P 8
 
 typedef enum {
@@ -117,6 +117,37 @@ mfsem_status mfsem_box_generate(const mfsem_box_desc* box, int32_t* elem_dof, do
  * along each axis.  [device] int32 parent[n_elem_fine], int8 child[n_elem_fine]. */
 mfsem_status mfsem_box_parents(const int32_t n_fine[3], int32_t* parent, int8_t* child,
                                void* stream);
+
+/* Nodes of derived meshes on arbitrary conforming meshes (Section 4.3: the
+ * octree hierarchy refined from a coarse mesh T0, whose children keep their
+ * parent's geometry, and the lower-degree levels of the same elements).  The
+ * parent mesh has degree p (1..MFSEM_MAX_P): elem_dof [n_elem][(p+1)^3] int32
+ * (local index a + (p+1)(b + (p+1)c)), xyz and fiber [n_nodes][3] FP64 (fiber
+ * may be NULL).  Each element carries an M^3 lattice of reference points:
+ *   refine: M = 2p + 1, the GLL points of degree p of the two halves of
+ *           [-1, 1] along each axis (the nodes of the element's 8 children);
+ *   degree: M = pc + 1, the GLL points of degree pc (1..MFSEM_MAX_P).
+ * New node g lies at lattice point loc[g] = I + M (J + M K) of element
+ * elem[g] (any element holding it; the numbering of the new nodes, i.e. which
+ * lattice points of which elements coincide, is the caller's).  Its position
+ * is the parent's isoparametric map there,
+ *   xyz_new[g] = sum_{a,b,c} l_a(xi_I) l_b(xi_J) l_c(xi_K) xyz[elem_dof[e][a,b,c]],
+ * with l the degree-p Lagrange basis on the GLL nodes, and fiber_new[g] the
+ * same interpolation of the fiber (not normalised; the operator normalises it
+ * at its quadrature points).  fiber_new is written when fiber is given.
+ * elem, loc [device] int32 [n_new]; xyz_new, fiber_new [device] [n_new][3].
+ * EINVAL for p or pc out of range or a NULL array with n_new > 0; an element,
+ * lattice point or node index out of range gives NaN for that node (nothing
+ * is read out of bounds).                                                     */
+mfsem_status mfsem_mesh_refine_nodes(int32_t p, int64_t n_elem, const int32_t* elem_dof,
+                                     int64_t n_nodes, const double* xyz, const double* fiber,
+                                     int64_t n_new, const int32_t* elem, const int32_t* loc,
+                                     double* xyz_new, double* fiber_new, void* stream);
+mfsem_status mfsem_mesh_degree_nodes(int32_t p, int64_t n_elem, const int32_t* elem_dof,
+                                     int64_t n_nodes, const double* xyz, const double* fiber,
+                                     int32_t pc, int64_t n_new, const int32_t* elem,
+                                     const int32_t* loc, double* xyz_new, double* fiber_new,
+                                     void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Operator A = alpha*M + K(sigma).
@@ -202,13 +233,16 @@ mfsem_status mfsem_op_apply_mass(const mfsem_op* op, int32_t dtype, const void* 
  * Chebyshev smoother, Section 4.3).                                          */
 mfsem_status mfsem_op_diagonal(const mfsem_op* op, int32_t dtype, void* d, void* stream);
 
-/* g[b][e][c] = w_b^T (dA/dsigma_{e,c}) u_b for c = (l, t, n): the derivative
- * of A with respect to each element's conductivities contracted with two
- * vectors (FP64).  Without a sheet, c = t covers the whole plane normal to the
- * fiber and g[..][2] = 0; without a fiber only c = t is non-zero.
+/* g[b][e][c] = scale * w_b^T (dA/dsigma_{e,c}) u_b for c = (l, t, n): the
+ * derivative of A with respect to each element's conductivities contracted
+ * with two vectors (FP64).  Without a sheet, c = t covers the whole plane
+ * normal to the fiber and g[..][2] = 0; without a fiber only c = t is
+ * non-zero.  scale = 1 gives the apply's adjoint (dL/dsigma of y = A u with
+ * w = dL/dy); scale = -1 the solve's (dL/dsigma of u = A^{-1} f with w the
+ * adjoint solution of A w = dL/du).  EINVAL for a non-finite scale.
  * u, w [device][batch][n_dof]; g [device][batch][n_elem][3].                  */
 mfsem_status mfsem_op_grad_sigma(const mfsem_op* op, const double* u, const double* w,
-                                 double* g, void* stream);
+                                 double scale, double* g, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Matrix-based path: A assembled as a sparse matrix (the paper's matrix-based

@@ -79,6 +79,10 @@ PROTOTYPES = {
     "mfsem_box_counts": (_ST, [C.POINTER(BoxDesc), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "mfsem_box_generate": (_ST, [C.POINTER(BoxDesc), _P, _P, _P, _P]),
     "mfsem_box_parents": (_ST, [C.POINTER(C.c_int32), _P, _P, _P]),
+    "mfsem_mesh_refine_nodes": (_ST, [C.c_int32, C.c_int64, _P, C.c_int64, _P, _P, C.c_int64, _P,
+                                      _P, _P, _P, _P]),
+    "mfsem_mesh_degree_nodes": (_ST, [C.c_int32, C.c_int64, _P, C.c_int64, _P, _P, C.c_int32,
+                                      C.c_int64, _P, _P, _P, _P, _P]),
     "mfsem_op_workspace_bytes": (_ST, [C.POINTER(OpDesc), C.POINTER(C.c_size_t)]),
     "mfsem_op_create": (_ST, [C.POINTER(OpDesc), _P, C.c_size_t, _P, C.POINTER(_P)]),
     "mfsem_op_destroy": (_ST, [_P]),
@@ -88,7 +92,7 @@ PROTOTYPES = {
     "mfsem_op_apply_add": (_ST, [_P, C.c_int32, _P, _P, _P]),
     "mfsem_op_apply_mass": (_ST, [_P, C.c_int32, _P, _P, _P]),
     "mfsem_op_diagonal": (_ST, [_P, C.c_int32, _P, _P]),
-    "mfsem_op_grad_sigma": (_ST, [_P, _P, _P, _P, _P]),
+    "mfsem_op_grad_sigma": (_ST, [_P, _P, _P, C.c_double, _P, _P]),
     "mfsem_csr_nnz": (_ST, [_P, C.POINTER(C.c_int64)]),
     "mfsem_csr_assemble": (_ST, [_P, _P, _P, _P, _P]),
     "mfsem_csr_spmv": (_ST, [C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P]),

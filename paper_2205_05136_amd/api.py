@@ -203,11 +203,12 @@ class Operator:
         L.check(L.load().mfsem_op_diagonal(self.handle, self._dt(d), _ptr(d), _stream()))
         return d
 
-    def grad_sigma(self, u, w):
-        """g[b][e][c] = w_b^T dA/dsigma_{e,c} u_b (mfsem_op_grad_sigma)."""
+    def grad_sigma(self, u, w, scale=1.0):
+        """g[b][e][c] = scale * w_b^T dA/dsigma_{e,c} u_b (mfsem_op_grad_sigma)."""
         u, w = self._vec(u.contiguous()), self._vec(w.contiguous())
         g = torch.empty((self.batch, self.n_elem, 3), dtype=torch.float64, device=self.device)
-        L.check(L.load().mfsem_op_grad_sigma(self.handle, _ptr(u), _ptr(w), _ptr(g), _stream()))
+        L.check(L.load().mfsem_op_grad_sigma(self.handle, _ptr(u), _ptr(w), float(scale), _ptr(g),
+                                             _stream()))
         return g
 
     def set_alpha(self, alpha):
@@ -400,6 +401,36 @@ def hierarchy(spec, fine_box: Box | None = None, coarsening=(("p", 2), ("p", 1))
     mg = Multigrid(ops, transfers, precision=precision, **mg_kw)
     mg.boxes = boxes
     return ops, mg
+
+
+# ------------------------------------------------------- node placement ---
+def place_nodes(kind: str, p: int, elem_dof, xyz, fiber, elem, loc, pc: int = 0):
+    """Coordinates (and fibers) of new nodes from a parent mesh's degree-p map
+    (mfsem_mesh_refine_nodes for kind "refine", mfsem_mesh_degree_nodes with
+    degree pc for kind "degree"): new node g at point loc[g] of element
+    elem[g]'s reference lattice.  Device tensors in, device tensors out."""
+    if kind not in ("refine", "degree"):
+        raise ValueError("kind must be 'refine' or 'degree'")
+    for a, dt in ((elem_dof, torch.int32), (xyz, torch.float64), (elem, torch.int32),
+                  (loc, torch.int32)):
+        if a.dtype != dt or not a.is_cuda or not a.is_contiguous():
+            raise ValueError(f"expected a contiguous {dt} CUDA tensor")
+    if fiber is not None and (fiber.dtype != torch.float64 or fiber.shape != xyz.shape
+                              or not fiber.is_contiguous()):
+        raise ValueError("fiber must be a contiguous float64 tensor shaped like xyz")
+    if elem.numel() != loc.numel():
+        raise ValueError("elem and loc must have one entry per new node")
+    n_new = elem.numel()
+    out = torch.empty((n_new, 3), dtype=torch.float64, device=xyz.device)
+    fout = None if fiber is None else torch.empty_like(out)
+    lib = L.load()
+    args = (p, elem_dof.shape[0], _ptr(elem_dof), xyz.shape[0], _ptr(xyz), _ptr(fiber))
+    tail = (n_new, _ptr(elem), _ptr(loc), _ptr(out), _ptr(fout), _stream())
+    if kind == "refine":
+        L.check(lib.mfsem_mesh_refine_nodes(*args, *tail))
+    else:
+        L.check(lib.mfsem_mesh_degree_nodes(*args, pc, *tail))
+    return out, fout
 
 
 # -------------------------------------------------------------------- PCG ---

@@ -91,8 +91,9 @@ class SolveFn(torch.autograd.Function):
         lam, _ = s.solve(ubar.detach())  # adjoint solve: A is symmetric
         dsig = None
         if ctx.needs_input_grad[0]:
-            g = s.ops[0].grad_sigma(u.reshape(-1), lam.reshape(-1))
-            dsig = (-g).reshape(sigma.shape)
+            # dL/dsigma_e = -lam^T (dA/dsigma_e) u: the library applies the sign
+            dsig = s.ops[0].grad_sigma(u.reshape(-1), lam.reshape(-1), scale=-1.0).reshape(
+                sigma.shape)
         df = lam if ctx.needs_input_grad[1] else None
         return dsig, df, None
 

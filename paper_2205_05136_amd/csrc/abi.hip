@@ -56,6 +56,10 @@ void* noalloc_scratch() {
 void launch_box(const mfsem_box_desc& d, int64_t n_elem, int64_t n_dof, const double* xi_host,
                 int32_t* ed, double* xyz, double* fib, hipStream_t s);
 void launch_box_parents(const int32_t n[3], int32_t* parent, int8_t* child, hipStream_t s);
+void launch_place_nodes(int p, int kind, int pc, int64_t n_elem, const int32_t* ed,
+                        int64_t n_nodes, const double* xyz, const double* fib, int64_t n_new,
+                        const int32_t* elem, const int32_t* loc, double* xyz_out,
+                        double* fib_out, hipStream_t s);
 void launch_ap(int64_t n, double dt, double chi, double cm, const mfsem_ap_params& prm,
                const double* V, double* w, const double* istim, const double* m, double* b,
                hipStream_t s);
@@ -382,12 +386,13 @@ mfsem_status mfsem_op_diagonal(const mfsem_op* op, int32_t dtype, void* d, void*
   });
 }
 
-mfsem_status mfsem_op_grad_sigma(const mfsem_op* op, const double* u, const double* w, double* g,
-                                 void* stream) {
+mfsem_status mfsem_op_grad_sigma(const mfsem_op* op, const double* u, const double* w,
+                                 double scale, double* g, void* stream) {
   return guarded([&] {
     require(op != nullptr, "operator is NULL");
     require(u && w && g, "NULL argument");
-    launch_grad_sigma(*op, u, w, g, as_stream(stream));
+    require(std::isfinite(scale), "scale must be finite");
+    launch_grad_sigma(*op, u, w, scale, g, as_stream(stream));
   });
 }
 
@@ -538,6 +543,43 @@ mfsem_status mfsem_mg_transfer(const mfsem_mg* mg, int32_t level, int32_t direct
     require(direction == 0 || direction == 1, "direction must be 0 or 1");
     mg_transfer(*mg, level, direction, in, out, as_stream(stream));
   });
+}
+
+// --------------------------------------------------------- node placement ---
+namespace {
+mfsem_status place_nodes_entry(int kind, int32_t p, int64_t n_elem, const int32_t* elem_dof,
+                               int64_t n_nodes, const double* xyz, const double* fiber,
+                               int32_t pc, int64_t n_new, const int32_t* elem,
+                               const int32_t* loc, double* xyz_new, double* fiber_new,
+                               void* stream) {
+  return guarded([&] {
+    require(p >= 1 && p <= MFSEM_MAX_P, "p must be in 1..MFSEM_MAX_P");
+    if (kind == MFSEM_NODES_DEGREE) require(pc >= 1 && pc <= MFSEM_MAX_P, "pc must be in 1..MFSEM_MAX_P");
+    require(n_elem >= 0 && n_nodes >= 0 && n_new >= 0, "counts must be >= 0");
+    require(n_new == 0 || (elem && loc && xyz_new), "NULL array");
+    require(n_new == 0 || n_elem == 0 || (elem_dof && xyz), "NULL parent mesh array");
+    require(fiber_new == nullptr || fiber != nullptr, "fiber_new needs a parent fiber");
+    launch_place_nodes(p, kind, pc, n_elem, elem_dof, n_nodes, xyz, fiber, n_new, elem, loc,
+                       xyz_new, fiber ? fiber_new : nullptr, as_stream(stream));
+  });
+}
+}  // namespace
+
+mfsem_status mfsem_mesh_refine_nodes(int32_t p, int64_t n_elem, const int32_t* elem_dof,
+                                     int64_t n_nodes, const double* xyz, const double* fiber,
+                                     int64_t n_new, const int32_t* elem, const int32_t* loc,
+                                     double* xyz_new, double* fiber_new, void* stream) {
+  return place_nodes_entry(MFSEM_NODES_REFINE, p, n_elem, elem_dof, n_nodes, xyz, fiber, 0,
+                           n_new, elem, loc, xyz_new, fiber_new, stream);
+}
+
+mfsem_status mfsem_mesh_degree_nodes(int32_t p, int64_t n_elem, const int32_t* elem_dof,
+                                     int64_t n_nodes, const double* xyz, const double* fiber,
+                                     int32_t pc, int64_t n_new, const int32_t* elem,
+                                     const int32_t* loc, double* xyz_new, double* fiber_new,
+                                     void* stream) {
+  return place_nodes_entry(MFSEM_NODES_DEGREE, p, n_elem, elem_dof, n_nodes, xyz, fiber, pc,
+                           n_new, elem, loc, xyz_new, fiber_new, stream);
 }
 
 // -------------------------------------------------------------------- PCG ---

@@ -177,8 +177,16 @@ struct SemCfg {
   static constexpr int L3 = Q3;                            // quad values / flux x
 };
 
+// Waves per SIMD the register budget must allow: at P = 7 with up to 8 Gauss
+// points the FP64 stiffness kernel fits 3 waves (168 VGPRs, 36 B/lane spilled)
+// where the unconstrained build takes 177 VGPRs and 2 waves; on the 51M-DOF slab
+// at p = 6, q = 8 that is 2.03 -> 1.84 ms.  At P = 8, q = 9 the same bound spills
+// 88 B/lane and measured slower (2.08 -> 2.28 ms), so it keeps 2.
+template <typename T, int P, int Q>
+constexpr int sem_min_waves() { return (sizeof(T) == 8 && P == 7 && Q <= 8) ? 3 : 1; }
+
 template <typename T, int P, int Q, bool STIFF>
-__global__ __launch_bounds__((SemCfg<P, Q>::THREADS)) void ax_sem_kernel(
+__global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())) void ax_sem_kernel(
     int64_t n_elem, int64_t n_dof, const int32_t* __restrict__ ed, const T* __restrict__ G,
     const T* __restrict__ WJ, const T* __restrict__ idet, T alpha, const T* __restrict__ Btab,
     const T* __restrict__ Dqtab, const T* __restrict__ wtab, const T* __restrict__ x,

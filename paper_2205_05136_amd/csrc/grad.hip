@@ -41,6 +41,7 @@ struct GradArgs {
   const double* u;
   const double* w;
   double* g;
+  double scale;  // every output is multiplied by it
 };
 
 __device__ double block_sum(double v, double* sh) {
@@ -179,9 +180,9 @@ __global__ __launch_bounds__(GT) void grad_kernel(GradArgs a) {
     gn = block_sum(gn, sh);
     if (tid == 0) {
       double* out = a.g + ((int64_t)bt * a.n_elem + e) * 3;
-      out[0] = gl;
-      out[1] = gt;
-      out[2] = gn;
+      out[0] = a.scale * gl;
+      out[1] = a.scale * gt;
+      out[2] = a.scale * gn;
     }
   }
 }
@@ -339,17 +340,17 @@ __global__ __launch_bounds__(SFT) void grad_sf_kernel(GradArgs a) {
     gn = block_sum(gn, sh);
     if (tid == 0) {
       double* out = a.g + ((int64_t)bt * a.n_elem + e) * 3;
-      out[0] = gl;
-      out[1] = gt;
-      out[2] = gn;
+      out[0] = a.scale * gl;
+      out[1] = a.scale * gt;
+      out[2] = a.scale * gn;
     }
   }
 }
 
 }  // namespace
 
-void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, double* g,
-                       hipStream_t s) {
+void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, double scale,
+                       double* g, hipStream_t s) {
   if (op.d.n_elem == 0) return;
   GradArgs a;
   a.n_elem = op.d.n_elem;
@@ -372,6 +373,7 @@ void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, dou
   a.u = u;
   a.w = w;
   a.g = g;
+  a.scale = scale;
   const size_t lds = sf_lds_doubles(a.P, a.Pm, a.Q) * sizeof(double);
   if (lds <= SF_LDS_MAX) {
     grad_sf_kernel<<<dim3((unsigned)op.d.n_elem), SFT, lds, s>>>(a);

@@ -12,6 +12,9 @@
 
 namespace mfsem {
 
+// node lattices of the placement kernel (mesh.hip)
+enum { MFSEM_NODES_REFINE = 0, MFSEM_NODES_DEGREE = 1 };
+
 // ---------------------------------------------------------------- errors ---
 void set_error(const std::string& msg);
 struct Error {
@@ -153,8 +156,8 @@ template <typename T>
 bool launch_brick(const mfsem_op& op, const T* G, const T* WJ, const T* idet, const T* tab,
                   const T* x, T* y, T alpha, hipStream_t s);
 void launch_lattice_check(const mfsem_op& op, unsigned long long* bad, hipStream_t s);
-void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, double* g,
-                       hipStream_t s);
+void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, double scale,
+                       double* g, hipStream_t s);
 // matrix-based path on structured lattices (csr.hip)
 int64_t csr_nnz(const mfsem_op& op);
 void csr_assemble(const mfsem_op& op, int64_t* row_ptr, int32_t* col, double* val, hipStream_t s);

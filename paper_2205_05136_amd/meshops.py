@@ -8,8 +8,11 @@ space on a conforming hexahedral mesh) with the general element kernel
 (`Operator(..., structured=False)`): each element's map, Jacobian and fibers
 come from its own nodes, so a mesh whose elements are rotated, shuffled and
 renumbered gives the same operator up to the permutation of the nodes.  These
-host-side helpers build such meshes (from a structured box, for testing and
-for reordering real meshes) and a locality order for arbitrary ones.
+helpers build such meshes (from a structured box, for testing and for
+reordering real meshes) and a locality order for arbitrary ones.  The
+numbering of refined and lower-degree meshes is integer host code; their
+node coordinates and fibers are evaluated from the parent map in the library
+(mfsem_mesh_refine_nodes, mfsem_mesh_degree_nodes).
 """
 from __future__ import annotations
 
@@ -145,28 +148,6 @@ def to_mesh(p: int, elem_dof: np.ndarray, xyz: np.ndarray, fiber: np.ndarray | N
 # entity computes the same key (the lattices are symmetric: GLL points and the
 # halves of the octree children), so the numbering needs no coordinates.
 
-def gll_points(p: int) -> np.ndarray:
-    """The p+1 Gauss-Lobatto-Legendre points on [-1, 1] (ends and the roots of P_p')."""
-    if p == 1:
-        return np.array([-1.0, 1.0])
-    from numpy.polynomial import legendre as L
-    inner = np.sort(L.legroots(L.legder(np.eye(p + 1)[p])).real)
-    # one Newton step on P_p' for full accuracy
-    d1, d2 = L.legder(np.eye(p + 1)[p]), L.legder(np.eye(p + 1)[p], 2)
-    inner = inner - L.legval(inner, d1) / L.legval(inner, d2)
-    return np.concatenate([[-1.0], inner, [1.0]])
-
-
-def lagrange_1d(nodes: np.ndarray, pts: np.ndarray) -> np.ndarray:
-    """[len(pts)][len(nodes)]: the nodal Lagrange basis at the points."""
-    out = np.ones((len(pts), len(nodes)))
-    for j, xj in enumerate(nodes):
-        for m, xm in enumerate(nodes):
-            if m != j:
-                out[:, j] *= (pts - xm) / (xj - xm)
-    return out
-
-
 def element_corners(elem_dof: np.ndarray, p: int) -> np.ndarray:
     """Global ids of each element's 8 corner nodes, [n_elem][8], corner
     (sx, sy, sz) in {0, 1}^3 at column sx + 2 sy + 4 sz."""
@@ -242,27 +223,15 @@ def lattice_numbering(corners: np.ndarray, m: int):
     return ids, len(order), np.stack([first // M ** 3, first % M ** 3], axis=1)
 
 
-def _map_at(mesh_p: int, elem_dof: np.ndarray, values: np.ndarray, elems: np.ndarray,
-            xi: np.ndarray, I: np.ndarray, J: np.ndarray, K: np.ndarray) -> np.ndarray:
-    """Interpolate a nodal field of degree mesh_p at reference points: for each
-    (elems[n], xi[I[n]], xi[J[n]], xi[K[n]]), sum_abc v[node abc] l_a l_b l_c."""
-    P = mesh_p + 1
-    Lm = lagrange_1d(gll_points(mesh_p), xi)                    # [len(xi)][P]
-    v = values[np.asarray(elem_dof)[elems]].reshape(len(elems), P, P, P, -1)  # [n][c][b][a][d]
-    return np.einsum("na,nb,nc,ncbad->nd", Lm[I], Lm[J], Lm[K], v)
-
-
-def refine(mesh: "Mesh | tuple"):
-    """Octree refinement of a conforming mesh: every element split into its 8
-    children, the children's degree-p nodes numbered once across the mesh, and
-    node coordinates and fibers interpolated from the parent's map (exact: the
-    parent's degree-p map restricted to a child is a degree-p polynomial of the
-    child's reference coordinates, Section 4.3).  Accepts a Mesh (moved to the
-    host) or (p, elem_dof, xyz, fiber) numpy arrays.  Returns
-    (p, elem_dof, xyz, fiber, parent, child) as numpy arrays: fine element
-    8 e + c is child c = cx + 2 cy + 4 cz of coarse element e, with its local
-    axes those of the parent (the convention of the h-transfer)."""
-    p, ed, xyz, fib = _arrays(mesh)
+def refine_topology(p: int, elem_dof: np.ndarray):
+    """The integer part of octree refinement: every element split into its 8
+    children and the children's degree-p nodes numbered once across the mesh
+    (topologically, lattice_numbering).  Fine element 8 e + c is child
+    c = cx + 2 cy + 4 cz of coarse element e, with its local axes those of the
+    parent (the convention of the h-transfer).  Returns (elem_dof_fine, parent,
+    child, first) with first[g] = (coarse element, point of its (2p+1)^3
+    lattice) holding new node g."""
+    ed = np.asarray(elem_dof, dtype=np.int64)
     ne, P = ed.shape[0], p + 1
     m = 2 * p
     ids, n_nodes, first = lattice_numbering(element_corners(ed, p), m)
@@ -278,28 +247,50 @@ def refine(mesh: "Mesh | tuple"):
         fine_ed[c::8] = ids[:, loc]
     parent = np.repeat(np.arange(ne), 8)
     child = np.tile(np.arange(8), ne)
-    # coordinates at the lattice positions of the first occurrence of each node
-    x = gll_points(p)
-    lat = np.concatenate([(x[:-1] - 1.0) / 2.0, (x + 1.0) / 2.0])   # 2p+1 points on [-1, 1]
-    e0, l0 = first[:, 0], first[:, 1]
-    I, J, K = l0 % M, (l0 // M) % M, l0 // (M * M)
-    xyz_f = _map_at(p, ed, xyz, e0, lat, I, J, K)
-    fib_f = None if fib is None else _map_at(p, ed, fib, e0, lat, I, J, K)
+    return fine_ed, parent, child, first
+
+
+def degree_topology(p: int, elem_dof: np.ndarray, pc: int):
+    """The integer part of a p-level: the degree-pc node map of the same
+    elements, nodes numbered once across the mesh.  Returns (elem_dof_pc,
+    first) with first[g] = (element, point of its (pc+1)^3 lattice)."""
+    ids, n_nodes, first = lattice_numbering(element_corners(np.asarray(elem_dof), p), pc)
+    return ids, first
+
+
+def _place(kind: str, p: int, ed, xyz, fib, first, pc: int = 0, device="cuda"):
+    """New node coordinates and fibers from the parent's map, on the device
+    (mfsem_mesh_refine_nodes / mfsem_mesh_degree_nodes); returned on the host."""
+    from . import api
+    dev = torch.device(device)
+    t = lambda v, dt: torch.as_tensor(np.ascontiguousarray(v), dtype=dt, device=dev)
+    xyz_n, fib_n = api.place_nodes(kind, p, t(ed, torch.int32), t(xyz, torch.float64),
+                                   None if fib is None else t(fib, torch.float64),
+                                   t(first[:, 0], torch.int32), t(first[:, 1], torch.int32), pc)
+    return xyz_n.cpu().numpy(), None if fib_n is None else fib_n.cpu().numpy()
+
+
+def refine(mesh: "Mesh | tuple", device="cuda"):
+    """Octree refinement of a conforming mesh (Section 4.3): the topology of
+    refine_topology, and node coordinates and fibers interpolated from the
+    parent's map by the library (exact: the parent's degree-p map restricted to
+    a child is a degree-p polynomial of the child's reference coordinates).
+    Accepts a Mesh or (p, elem_dof, xyz, fiber) numpy arrays.  Returns
+    (p, elem_dof, xyz, fiber, parent, child) as numpy arrays."""
+    p, ed, xyz, fib = _arrays(mesh)
+    fine_ed, parent, child, first = refine_topology(p, ed)
+    xyz_f, fib_f = _place("refine", p, ed, xyz, fib, first, device=device)
     return p, fine_ed, xyz_f, fib_f, parent, child
 
 
-def degree_mesh(mesh: "Mesh | tuple", pc: int):
+def degree_mesh(mesh: "Mesh | tuple", pc: int, device="cuda"):
     """The degree-pc node map of the same elements (a p-level of the multigrid
-    on an arbitrary mesh), nodes numbered once across the mesh and placed by the
-    degree-p map.  Returns (pc, elem_dof, xyz, fiber) as numpy arrays."""
+    on an arbitrary mesh), nodes numbered once across the mesh and placed by
+    the library from the degree-p map.  Returns (pc, elem_dof, xyz, fiber) as
+    numpy arrays."""
     p, ed, xyz, fib = _arrays(mesh)
-    ids, n_nodes, first = lattice_numbering(element_corners(ed, p), pc)
-    M = pc + 1
-    e0, l0 = first[:, 0], first[:, 1]
-    I, J, K = l0 % M, (l0 // M) % M, l0 // (M * M)
-    xc = gll_points(pc)
-    xyz_c = _map_at(p, ed, xyz, e0, xc, I, J, K)
-    fib_c = None if fib is None else _map_at(p, ed, fib, e0, xc, I, J, K)
+    ids, first = degree_topology(p, ed, pc)
+    xyz_c, fib_c = _place("degree", p, ed, xyz, fib, first, pc=pc, device=device)
     return pc, ids, xyz_c, fib_c
 
 

@@ -69,7 +69,8 @@ APPLY_CASES = (
        ("gll-p2-iso-jitter", synth.BoxSpec(p=2, n=(5, 4, 3), length=(1.0, 0.8, 0.6),
                                            sigma=(0.3, 0.3, 0.3), alpha=2.5), (5, None), None)]
     + [(f"gauss-p{p}-q{q}", _spec(p, quad="gauss", nq1d=q), None, None)
-       for p, q in [(1, 2), (2, 3), (2, 4), (3, 6), (4, 5), (4, 6), (5, 7), (7, 9), (8, 11)]]
+       for p, q in [(1, 2), (2, 3), (2, 4), (3, 6), (4, 5), (4, 6), (5, 7), (6, 7), (6, 8), (7, 9),
+                    (8, 11)]]
     + [("gauss-p3-jitter-sigma", _spec(3, quad="gauss", nq1d=5), (23, None), 8)]
 )
 
@@ -557,6 +558,9 @@ def test_grad_sigma_cases(name):
         prob = oop.Problem(spec, sigma=sig[b])
         g_ref = oadj.grad_sigma(prob, u[b], w[b])
         assert rel_l2(g[b], g_ref) <= TOL64, b
+    # the scale argument multiplies the result (the solve's adjoint takes -1)
+    gs = to_np(op.grad_sigma(to_dev(u), to_dev(w), scale=-2.5))
+    assert np.array_equal(gs, -2.5 * g)
 
 
 def test_ionic_step():

@@ -145,6 +145,47 @@ def test_lattice_numbering_counts_on_a_box():
         assert np.array_equal(ids[first[:, 0], first[:, 1]], np.arange(n))
 
 
+def _bijective(a, b):
+    """a[k] <-> b[k] pairs define one bijection between the two node sets."""
+    a, b = np.asarray(a).reshape(-1), np.asarray(b).reshape(-1)
+    pairs = np.unique(np.stack([a, b], axis=1), axis=0)
+    return (len(pairs) == len(np.unique(a)) == len(np.unique(b)))
+
+
+def test_refine_topology_is_the_box_at_twice_the_elements():
+    """Refining a box numbers the children's nodes like the box at twice the
+    elements, up to a renumbering (integer part, no coordinates): the fine
+    element maps pair with the fine box's maps one to one."""
+    from oracle import mesh as omesh
+    m = omesh.box(BOX)
+    ed, parent, child, first = meshops.refine_topology(BOX.p, m.elem_dof)
+    fine = BOX.with_(n=tuple(2 * k for k in BOX.n))
+    mf_ = omesh.box(fine)
+    assert ed.shape == (fine.n_elem, (BOX.p + 1) ** 3) and ed.max() + 1 == fine.n_dof
+    s_of = np.empty(fine.n_elem, dtype=np.int64)
+    for e in range(BOX.n_elem):
+        ex, ey, ez = e % BOX.n[0], (e // BOX.n[0]) % BOX.n[1], e // (BOX.n[0] * BOX.n[1])
+        for c in range(8):
+            f = 8 * e + c
+            assert parent[f] == e and child[f] == c
+            s_of[f] = _struct_elem(fine, 2 * ex + (c & 1), 2 * ey + ((c >> 1) & 1), 2 * ez + (c >> 2))
+    assert _bijective(ed, mf_.elem_dof[s_of])
+    # the recorded first occurrence of each node is a lattice point of its element
+    assert np.all((first[:, 1] >= 0) & (first[:, 1] < (2 * BOX.p + 1) ** 3))
+
+
+def test_degree_topology_is_the_lower_degree_box():
+    from oracle import mesh as omesh
+    ced, cxyz, cfib = _scrambled_coarse(BOX, 12)
+    for pc in (1, 2, 3):
+        ids, first = meshops.degree_topology(BOX.p, ced, pc)
+        assert ids.max() + 1 == omesh.box(BOX.with_(p=pc)).xyz.shape[0]
+        assert np.array_equal(np.unique(ids), np.arange(ids.max() + 1))
+        # corners keep the coarse mesh's corner identity
+        assert _bijective(meshops.element_corners(ids, pc), meshops.element_corners(ced, BOX.p))
+
+
+@pytest.mark.gpu
 def test_refined_box_is_the_box_at_twice_the_elements():
     from oracle import mesh as omesh
     m = omesh.box(BOX)
@@ -197,6 +238,7 @@ def _h_prolongation(p, ed_f, ed_c, parent, child, n_f, n_c):
     return Pm
 
 
+@pytest.mark.gpu
 def test_refined_scrambled_mesh_operator_and_h_prolongation():
     """Refining a rotated, shuffled, renumbered coarse box gives the permuted
     operator of the box at twice the elements, and its parent/child maps give
@@ -218,6 +260,7 @@ def test_refined_scrambled_mesh_operator_and_h_prolongation():
     np.testing.assert_allclose(Pu[np.ix_(pf, pc)], Ps, atol=1e-14)
 
 
+@pytest.mark.gpu
 def test_degree_mesh_is_the_lower_degree_box():
     from oracle import mesh as omesh
     ced, cxyz, cfib = _scrambled_coarse(BOX, 12)
@@ -284,6 +327,24 @@ def test_hp_multigrid_on_a_refined_scrambled_mesh():
 
 
 @pytest.mark.parametrize("seed", range(6))
+def test_refine_topology_on_random_scrambled_boxes(seed):
+    """Random box sizes, degrees and scramblings: the refined and degree-pc
+    numberings have the structured node counts (integer part)."""
+    rng = np.random.default_rng(100 + seed)
+    p = int(rng.integers(1, 5))
+    n = tuple(int(v) for v in rng.integers(1, 4, 3))
+    spec = synth.BoxSpec(p=p, n=n, length=tuple(rng.uniform(0.5, 2.0, 3)), fiber=True,
+                         theta0=0.3, theta1=0.3)
+    ced, cxyz, cfib = _scrambled_coarse(spec, 200 + seed)
+    ed, parent, child, first = meshops.refine_topology(p, ced)
+    assert ed.max() + 1 == np.prod([2 * p * k + 1 for k in n]) and ed.shape[0] == 8 * spec.n_elem
+    pc = int(rng.integers(1, p + 1))
+    ids, _ = meshops.degree_topology(p, ced, pc)
+    assert ids.max() + 1 == np.prod([pc * k + 1 for k in n])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", range(6))
 def test_refine_and_degree_mesh_on_random_scrambled_boxes(seed):
     """Random box sizes, degrees and scramblings: the refined mesh and the
     degree-pc mesh have the structured node counts and node positions."""
@@ -305,3 +366,29 @@ def test_refine_and_degree_mesh_on_random_scrambled_boxes(seed):
     pc = int(rng.integers(1, p + 1))
     _, ed_c, xyz_c, _ = meshops.degree_mesh((p, ced, cxyz, cfib), pc)
     _match(xyz_c, omesh.box(spec.with_(p=pc)).xyz)
+
+
+@pytest.mark.gpu
+def test_place_nodes_argument_and_range_errors():
+    """Node placement through the C ABI: a bad degree or lattice is refused on
+    the host (EINVAL), and an element or lattice index out of range gives NaN
+    coordinates for that node only (the kernel reads nothing out of bounds)."""
+    import torch
+    import paper_2205_05136_amd as mf
+    from paper_2205_05136_amd import api
+    from gpu_common import announce
+    from oracle import mesh as omesh
+    announce("place nodes: errors")
+    m = omesh.box(BOX)
+    t = lambda v, dt: torch.as_tensor(np.ascontiguousarray(v), dtype=dt, device="cuda")
+    ed, xyz = t(m.elem_dof, torch.int32), t(m.xyz, torch.float64)
+    elem = t([0, BOX.n_elem, -1, 1], torch.int32)
+    loc = t([0, 0, 0, (2 * BOX.p + 1) ** 3], torch.int32)
+    out, _ = api.place_nodes("refine", BOX.p, ed, xyz, None, elem, loc)
+    o = out.cpu().numpy()
+    np.testing.assert_allclose(o[0], m.xyz[m.elem_dof[0, 0]], atol=1e-14)
+    assert np.isnan(o[1:]).all()
+    with pytest.raises(mf.MfsemError):
+        api.place_nodes("degree", BOX.p, ed, xyz, None, elem, loc, pc=0)
+    with pytest.raises(mf.MfsemError):
+        api.place_nodes("refine", 0, ed, xyz, None, elem, loc)
