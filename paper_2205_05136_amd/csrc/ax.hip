@@ -177,13 +177,12 @@ struct SemCfg {
   static constexpr int L3 = Q3;                            // quad values / flux x
 };
 
-// Waves per SIMD the register budget must allow: at P = 7 with up to 8 Gauss
-// points the FP64 stiffness kernel fits 3 waves (168 VGPRs, 36 B/lane spilled)
-// where the unconstrained build takes 177 VGPRs and 2 waves; on the 51M-DOF slab
-// at p = 6, q = 8 that is 2.03 -> 1.84 ms.  At P = 8, q = 9 the same bound spills
-// 88 B/lane and measured slower (2.08 -> 2.28 ms), so it keeps 2.
+// Waves per SIMD the register budget must allow: 3 for the FP64 kernels from
+// P = 6 with up to 9 Gauss points (at P = 8, Q = 9: 168 VGPRs with 24 B/lane
+// spilled, against 183 VGPRs and 2 waves unconstrained; the LDS of three
+// 3-element workgroups fits a CU).
 template <typename T, int P, int Q>
-constexpr int sem_min_waves() { return (sizeof(T) == 8 && P == 7 && Q <= 8) ? 3 : 1; }
+constexpr int sem_min_waves() { return (sizeof(T) == 8 && P >= 6 && Q <= 9) ? 3 : 1; }
 
 template <typename T, int P, int Q, bool STIFF>
 __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())) void ax_sem_kernel(
@@ -216,13 +215,9 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
   T* b2 = s2 + le * C::L2;
   T* b3 = s3 + le * C::L3;
 
-  int gi[P];
   if (node) {
 #pragma unroll
-    for (int c = 0; c < P; ++c) {
-      gi[c] = ed[e * P3 + c * P2 + j * P + i];
-      b1[c * P2 + j * P + i] = x[gi[c]];
-    }
+    for (int c = 0; c < P; ++c) b1[c * P2 + j * P + i] = x[ed[e * P3 + c * P2 + j * P + i]];
   }
   __syncthreads();
   // x-interpolation: b2[c][b][k1] = sum_a B[k1][a] u[c][b][a]
@@ -247,15 +242,14 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
     }
   }
   __syncthreads();
-  // z-interpolation into registers and b3[k3][k2][k1]
-  T uq[Q];
+  // z-interpolation into b3[k3][k2][k1] (the lane's own column is read back
+  // from there, so the values need no registers between the phases)
   if (active) {
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < P; ++c) s += sB[k * P + c] * b1[c * Q2 + j * Q + i];
-      uq[k] = s;
+      for (int c = 0; c < P; ++c) s += Btab[k * P + c] * b1[c * Q2 + j * Q + i];
       b3[k * Q2 + j * Q + i] = s;
     }
   }
@@ -272,7 +266,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
         for (int m = 0; m < Q; ++m) {
           sx += sDq[i * Q + m] * b3[k * Q2 + j * Q + m];
           sy += sDq[j * Q + m] * b3[k * Q2 + m * Q + i];
-          sz += sDq[k * Q + m] * uq[m];
+          sz += Dqtab[k * Q + m] * b3[m * Q2 + j * Q + i];
         }
         dx[k] = sx;
         dy[k] = sy;
@@ -294,6 +288,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
         load_g6(Ge + (int64_t)q * 6, g6);
         const T g00 = g6[0], g01 = g6[1], g02 = g6[2];
         const T g11 = g6[3], g12 = g6[4], g22 = g6[5];
+        const T uk = b3[q];  // this lane's value, read before its flux overwrites it
         b3[q] = g00 * dx[k] + g01 * dy[k] + g02 * dz[k];
         b2[q] = g01 * dx[k] + g11 * dy[k] + g12 * dz[k];
         fz[k] = g02 * dx[k] + g12 * dy[k] + g22 * dz[k];
@@ -305,7 +300,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
         } else {
           wj = WJ[e * Q3 + q];
         }
-        rq[k] = alpha * wj * uq[k];
+        rq[k] = alpha * wj * uk;
       }
     }
     __syncthreads();
@@ -317,7 +312,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
         for (int m = 0; m < Q; ++m) {
           v += sDq[m * Q + i] * b3[k * Q2 + j * Q + m];
           v += sDq[m * Q + j] * b2[k * Q2 + m * Q + i];
-          v += sDq[m * Q + k] * fz[m];
+          v += Dqtab[m * Q + k] * fz[m];
         }
         rq[k] = v;
       }
@@ -325,7 +320,8 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
   } else {
     if (active) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) rq[k] = alpha * WJ[e * Q3 + k * Q2 + j * Q + i] * uq[k];
+      for (int k = 0; k < Q; ++k)
+        rq[k] = alpha * WJ[e * Q3 + k * Q2 + j * Q + i] * b3[k * Q2 + j * Q + i];
     }
   }
   // back to the nodes: z-pass from registers into b1[c][k2][k1]
@@ -334,7 +330,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
     for (int c = 0; c < P; ++c) {
       T s = 0;
 #pragma unroll
-      for (int k = 0; k < Q; ++k) s += sB[k * P + c] * rq[k];
+      for (int k = 0; k < Q; ++k) s += Btab[k * P + c] * rq[k];
       b1[c * Q2 + j * Q + i] = s;
     }
   }
@@ -357,7 +353,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
       T s = 0;
 #pragma unroll
       for (int k = 0; k < Q; ++k) s += sB[k * P + i] * b2[c * P * Q + j * Q + k];
-      atomic_add(&y[gi[c]], s);
+      atomic_add(&y[ed[e * P3 + c * P2 + j * P + i]], s);
     }
   }
 }

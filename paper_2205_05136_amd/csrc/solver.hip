@@ -308,10 +308,7 @@ void mg_setup(mfsem_mg& mg, hipStream_t s) {
       MFSEM_HIP(hipStreamSynchronize(s));
       L.lattice = bad == 0;
     }
-    if (l + 1 < mg.lv.size() && L.lattice) {
-      MFSEM_HIP(hipStreamSynchronize(s));
-      lattice_transfer_upload(L.lt);
-    } else if (l + 1 < mg.lv.size()) {
+    if (l + 1 < mg.lv.size() && !L.lattice) {
       const mfsem_op& F = *L.op;
       const int P3 = F.P * F.P * F.P;
       if (f64) launch_inv_multiplicity<double>(F.d.elem_dof, F.d.n_elem, P3, L.n, P_<double>(L.wmult), s);

@@ -10,13 +10,13 @@
 // start(e) the first coarse node of the coarse element holding e.  A fine node
 // on an element face gets the same value from both sides, so every fine node
 // is written once.  Restriction is the exact transpose: for each coarse node,
-// the sum over the fine nodes that reference it.  Each pass streams a lattice
-// with coalesced rows, without index arrays over elements, atomics or
-// multiplicity weights.
+// the sum over the fine nodes that reference it.  Each pass runs one thread per
+// coarse element of a lattice line (lanes along x for the y and z passes, so
+// their loads and stores are coalesced rows), reading each input value about
+// once, without index arrays over elements, atomics or multiplicity weights.
 #include "transfer_lattice.hpp"
 
 #include <algorithm>
-#include <utility>
 
 namespace mfsem {
 
@@ -29,58 +29,121 @@ struct Dims {
   int ix, iy;      // input lattice (x and y extents; z follows from the pass)
 };
 
-// One pass along axis AX.  Forward (!BWD): out(o) = sum_m coef[o][m] in(idx[o] + m);
-// transposed: out(o) = sum_m coef[o][m] in(idx[o][m]); o is the output
-// coordinate along AX and the other two coordinates are kept.  SUB reads
-// in - in2; ACC adds into out; with zero, zero[out index] = 0 as well.
-// Grid: x over the output's (x, y) plane, y over its z, z over the batch.
-template <typename T, int AX, bool BWD, bool SUB, bool ACC>
-__global__ __launch_bounds__(LT) void lattice_pass_kernel(
-    const T* __restrict__ in, const T* __restrict__ in2, T* __restrict__ out, T* __restrict__ zero,
-    Dims d, int64_t n_in, const int32_t* __restrict__ idx, const T* __restrict__ coef, int W) {
-  const uint32_t plane = (uint32_t)d.ox * (uint32_t)d.oy;
-  const uint32_t t = blockIdx.x * LT + threadIdx.x;
-  if (t >= plane) return;
-  const int z = blockIdx.y;
-  const int64_t bt = blockIdx.z;
-  const int x = (int)(t % (uint32_t)d.ox), y = (int)(t / (uint32_t)d.ox);
-  const int o = AX == 0 ? x : (AX == 1 ? y : z);
-  const int64_t sx = 1, sy = d.ix, sz = (int64_t)d.ix * d.iy;
-  const int64_t sa = AX == 0 ? sx : (AX == 1 ? sy : sz);
-  // input offset with the pass coordinate at 0
-  const int64_t base = bt * n_in + (AX == 0 ? 0 : x) * sx + (AX == 1 ? 0 : (int64_t)y) * sy +
-                       (AX == 2 ? 0 : (int64_t)z) * sz;
-  const T* cf = coef + (int64_t)o * W;
-  T s = 0;
+// One 1D pass along axis AX, in element blocks.  Along the pass axis the fine
+// lattice is ne coarse elements of F fine intervals each (F = p_f for a
+// p-transfer, 2p for an h-transfer, the two children side by side), and the
+// 1D interpolation of one coarse element is the dense matrix M [F+1][PC1]
+// (row a: the coarse basis at the element's a-th fine node).  A fine node on
+// a coarse element boundary belongs to the element on its right (the last one
+// to the last element).  One thread per coarse element and line:
+//   forward:    fine a (owned) = sum_b M[a][b] coarse(E p_c + b);
+//   transposed: coarse b = sum over the element's owned fine a of M[a][b] fine,
+//               and the left vertex b = 0 also gathers the previous element's
+//               interior fine nodes with weights M[a][p_c];
+// each thread writes only the nodes it owns, so every output is written once
+// and no atomics are needed.  Each input value is read once by its element
+// (twice for the transposed pass's interior nodes next to a vertex), instead
+// of once per output that references it (up to 2 p_f + 1 times).
+template <typename T, int AX, bool BWD, bool SUB, bool ACC, int PC1>
+__global__ __launch_bounds__(LT) void lattice_elem_kernel(
+    const T* __restrict__ in, const T* __restrict__ in2, T* __restrict__ out,
+    T* __restrict__ zero, Dims d, int iz, int64_t n_in, int64_t n_out, ElemMat<T> m) {
+  const int64_t t = (int64_t)blockIdx.x * LT + threadIdx.x;
+  const int ne = m.ne, F = m.F;
+  // lines: the two axes other than AX, whose extents are the same in and out
+  const int e0 = AX == 0 ? ne : d.ox;
+  const int e1 = AX == 1 ? ne : d.oy;
+  const int e2 = AX == 2 ? ne : d.oz;
+  if (t >= (int64_t)e0 * e1 * e2) return;
+  const int c0 = (int)(t % e0);
+  const int c1 = (int)((t / e0) % e1);
+  const int c2 = (int)(t / ((int64_t)e0 * e1));
+  const int E = AX == 0 ? c0 : (AX == 1 ? c1 : c2);
+  const int64_t bt = blockIdx.y;
+  in += bt * n_in;
+  if (SUB) in2 += bt * n_in;
+  out += bt * n_out;
+  if (zero) zero += bt * n_out;
+  // strides of the input and output lattices, and the line's offset in each
+  const int64_t isy = d.ix, isz = (int64_t)d.ix * d.iy;
+  const int64_t osy = d.ox, osz = (int64_t)d.ox * d.oy;
+  const int64_t ia = AX == 0 ? 1 : (AX == 1 ? isy : isz);
+  const int64_t oa = AX == 0 ? 1 : (AX == 1 ? osy : osz);
+  const int64_t ibase = (AX == 0 ? 0 : c0) + (AX == 1 ? 0 : c1 * isy) + (AX == 2 ? 0 : c2 * isz);
+  const int64_t obase = (AX == 0 ? 0 : c0) + (AX == 1 ? 0 : c1 * osy) + (AX == 2 ? 0 : c2 * osz);
+  constexpr int PC = PC1 - 1;
+  const bool last = E == ne - 1;
+  (void)iz;
   if (!BWD) {
-    const int64_t k0 = base + (int64_t)idx[o] * sa;
-    for (int m = 0; m < W; ++m) {
-      const int64_t k = k0 + m * sa;
-      s += cf[m] * (SUB ? in[k] - in2[k] : in[k]);
+    T cv[PC1];
+#pragma unroll
+    for (int b = 0; b < PC1; ++b) cv[b] = in[ibase + (int64_t)(E * PC + b) * ia];
+    const int a_end = last ? F : F - 1;
+    for (int a = 0; a <= a_end; ++a) {
+      T s = 0;
+#pragma unroll
+      for (int b = 0; b < PC1; ++b) s += m.M[a * PC1 + b] * cv[b];
+      const int64_t o = obase + (int64_t)(E * F + a) * oa;
+      out[o] = ACC ? out[o] + s : s;
+      if (zero) zero[o] = T(0);
     }
   } else {
-    const int32_t* id = idx + (int64_t)o * W;
-    for (int m = 0; m < W; ++m) {
-      const int64_t k = base + (int64_t)id[m] * sa;
-      s += cf[m] * (SUB ? in[k] - in2[k] : in[k]);
+    T acc[PC1];
+#pragma unroll
+    for (int b = 0; b < PC1; ++b) acc[b] = 0;
+    const int a_end = last ? F : F - 1;
+    for (int a = 0; a <= a_end; ++a) {
+      const int64_t k = ibase + (int64_t)(E * F + a) * ia;
+      const T v = SUB ? in[k] - in2[k] : in[k];
+#pragma unroll
+      for (int b = 0; b < PC1; ++b) acc[b] += m.M[a * PC1 + b] * v;
     }
+    if (E > 0) {
+      for (int a = 1; a < F; ++a) {
+        const int64_t k = ibase + (int64_t)((E - 1) * F + a) * ia;
+        const T v = SUB ? in[k] - in2[k] : in[k];
+        acc[0] += m.M[a * PC1 + PC] * v;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < PC1; ++b)
+      if (b < PC || last) out[obase + (int64_t)(E * PC + b) * oa] = acc[b];
   }
-  const int64_t g = bt * ((int64_t)plane * d.oz) + (int64_t)z * plane + t;
-  out[g] = ACC ? out[g] + s : s;
-  if (zero) zero[g] = T(0);
+}
+
+template <typename T, int AX, bool BWD, bool SUB, bool ACC, int PC1>
+void elem_pass_pc(const T* in, const T* in2, T* out, T* zero, const int od[3], const int id[3],
+                  const ElemMat<T>& m, int batch, hipStream_t s) {
+  const int64_t lines = AX == 0 ? (int64_t)od[1] * od[2]
+                                : (AX == 1 ? (int64_t)od[0] * od[2] : (int64_t)od[0] * od[1]);
+  const int64_t threads = lines * m.ne;
+  if (threads == 0 || batch == 0) return;
+  const Dims d{od[0], od[1], od[2], id[0], id[1]};
+  const int64_t n_in = (int64_t)id[0] * id[1] * id[2];
+  const int64_t n_out = (int64_t)od[0] * od[1] * od[2];
+  const dim3 grid((unsigned)((threads + LT - 1) / LT), (unsigned)batch);
+  lattice_elem_kernel<T, AX, BWD, SUB, ACC, PC1>
+      <<<grid, LT, 0, s>>>(in, in2, out, zero, d, id[2], n_in, n_out, m);
+  MFSEM_LAUNCH("lattice_elem_kernel");
 }
 
 template <typename T, int AX, bool BWD, bool SUB, bool ACC>
-void pass(const T* in, const T* in2, T* out, T* zero, const int od[3], const int id[3],
-          const int32_t* idx, const void* coef, int W, int batch, hipStream_t s) {
-  const int64_t plane = (int64_t)od[0] * od[1];
-  if (plane == 0 || od[2] == 0 || batch == 0) return;
-  const Dims d{od[0], od[1], od[2], id[0], id[1]};
-  const int64_t n_in = (int64_t)id[0] * id[1] * id[2];
-  const dim3 grid((unsigned)((plane + LT - 1) / LT), (unsigned)od[2], (unsigned)batch);
-  lattice_pass_kernel<T, AX, BWD, SUB, ACC>
-      <<<grid, LT, 0, s>>>(in, in2, out, zero, d, n_in, idx, static_cast<const T*>(coef), W);
-  MFSEM_LAUNCH("lattice_pass_kernel");
+void elem_pass(const T* in, const T* in2, T* out, T* zero, const int od[3], const int id[3],
+               const ElemMat<T>& m, int batch, hipStream_t s) {
+  switch (m.pc1) {
+#define MFSEM_ELEM_CASE(K) \
+  case K: return elem_pass_pc<T, AX, BWD, SUB, ACC, K>(in, in2, out, zero, od, id, m, batch, s);
+    MFSEM_ELEM_CASE(2)
+    MFSEM_ELEM_CASE(3)
+    MFSEM_ELEM_CASE(4)
+    MFSEM_ELEM_CASE(5)
+    MFSEM_ELEM_CASE(6)
+    MFSEM_ELEM_CASE(7)
+    MFSEM_ELEM_CASE(8)
+    MFSEM_ELEM_CASE(9)
+#undef MFSEM_ELEM_CASE
+  }
+  fail(MFSEM_EUNSUPPORTED, "lattice transfer: coarse degree beyond the element-block kernels");
 }
 
 __global__ void box_parents_check_kernel(int n0, int n1, int64_t n_elem,
@@ -110,49 +173,11 @@ __global__ void parents_range_kernel(int64_t n_fine, int64_t n_coarse,
   if (cnt) atomicAdd(bad, cnt);
 }
 
-// 1D tables of one axis: forward (per fine node: first coarse node and Pc
-// coefficients) and transposed (per coarse node: fine nodes and coefficients).
-void build_axis(int kind, int pf, int pc, int nf_elem, const std::vector<double>& I,
-                LatticeAxisHost& h) {
-  const int Pf = pf + 1, Pc = pc + 1;
-  const bool hk = kind == MFSEM_TRANSFER_H;
+// Node counts of one axis: fine and coarse lattices.
+void axis_counts(int kind, int pf, int pc, int nf_elem, LatticeAxisHost& h) {
   h.nf = pf * nf_elem + 1;
-  h.nc = pc * (hk ? nf_elem / 2 : nf_elem) + 1;
-  h.Wf = Pc;
-  h.fstart.assign(h.nf, 0);
-  h.fcoef.assign((size_t)h.nf * Pc, 0.0);
-  std::vector<std::vector<std::pair<int, double>>> cols(h.nc);
-  for (int i = 0; i < h.nf; ++i) {
-    const int e = std::min(i / pf, nf_elem - 1), a = i - e * pf;
-    const int child = hk ? (e & 1) : 0;
-    const int ec = hk ? e / 2 : e;
-    h.fstart[i] = ec * pc;
-    for (int b = 0; b < Pc; ++b) {
-      const double c = I[(size_t)child * Pf * Pc + (size_t)a * Pc + b];
-      h.fcoef[(size_t)i * Pc + b] = c;
-      if (c != 0.0) cols[ec * pc + b].push_back({i, c});  // exact zeros add nothing
-    }
-  }
-  h.Wb = 1;
-  for (const auto& c : cols) h.Wb = std::max<int>(h.Wb, (int)c.size());
-  h.bidx.assign((size_t)h.nc * h.Wb, 0);
-  h.bcoef.assign((size_t)h.nc * h.Wb, 0.0);
-  for (int o = 0; o < h.nc; ++o)
-    for (size_t k = 0; k < cols[o].size(); ++k) {
-      h.bidx[(size_t)o * h.Wb + k] = cols[o][k].first;
-      h.bcoef[(size_t)o * h.Wb + k] = cols[o][k].second;
-    }
+  h.nc = pc * (kind == MFSEM_TRANSFER_H ? nf_elem / 2 : nf_elem) + 1;
 }
-
-void upload(void* dst, const std::vector<double>& v, size_t word) {
-  if (word == sizeof(double)) {
-    MFSEM_HIP(hipMemcpy(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
-  } else {
-    const std::vector<float> f(v.begin(), v.end());
-    MFSEM_HIP(hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
-  }
-}
-
 }  // namespace
 
 bool lattice_transfer_applies(const mfsem_op& fine, const mfsem_op& coarse, int kind) {
@@ -174,13 +199,27 @@ bool lattice_transfer_applies(const mfsem_op& fine, const mfsem_op& coarse, int 
 void lattice_transfer_layout(LatticeTransfer& t, const mfsem_op& fine, const mfsem_op& coarse,
                              int kind, int batch, size_t word, Arena& a) {
   const std::vector<double> I = transfer_matrices(kind, fine.P - 1, coarse.P - 1);
-  for (int d = 0; d < 3; ++d) build_axis(kind, fine.P - 1, coarse.P - 1, fine.lat[d], I, t.host[d]);
-  for (int d = 0; d < 3; ++d) {
-    const LatticeAxisHost& h = t.host[d];
-    t.fstart[d] = a.take_n<int32_t>(h.fstart.size());
-    t.fcoef[d] = a.take(h.fcoef.size() * word);
-    t.bidx[d] = a.take_n<int32_t>(h.bidx.size());
-    t.bcoef[d] = a.take(h.bcoef.size() * word);
+  for (int d = 0; d < 3; ++d) axis_counts(kind, fine.P - 1, coarse.P - 1, fine.lat[d], t.host[d]);
+  {
+    const int pf = fine.P - 1, Pf = fine.P, Pc = coarse.P;
+    const bool hk = kind == MFSEM_TRANSFER_H;
+    for (int d = 0; d < 3; ++d) {
+      ElemMat<double>& m = t.em64[d];
+      m.ne = coarse.lat[d];
+      m.F = hk ? 2 * pf : pf;
+      m.pc1 = Pc;
+      for (int a = 0; a <= m.F; ++a) {
+        const int child = (hk && a > pf) ? 1 : 0;
+        const int af = a - child * pf;
+        for (int b = 0; b < Pc; ++b)
+          m.M[a * Pc + b] = I[(size_t)child * Pf * Pc + (size_t)af * Pc + b];
+      }
+      ElemMat<float>& f = t.em32[d];
+      f.ne = m.ne;
+      f.F = m.F;
+      f.pc1 = m.pc1;
+      for (int i = 0; i < (m.F + 1) * Pc; ++i) f.M[i] = (float)m.M[i];
+    }
   }
   const int64_t nfx = t.host[0].nf, nfy = t.host[1].nf;
   const int64_t ncy = t.host[1].nc, ncz = t.host[2].nc;
@@ -188,18 +227,6 @@ void lattice_transfer_layout(LatticeTransfer& t, const mfsem_op& fine, const mfs
   t.s1 = a.take((size_t)(nfx * ncy * ncz) * batch * word);
   t.s2 = a.take((size_t)(nfx * nfy * ncz) * batch * word);
   t.word = word;
-}
-
-void lattice_transfer_upload(const LatticeTransfer& t) {
-  for (int d = 0; d < 3; ++d) {
-    const LatticeAxisHost& h = t.host[d];
-    MFSEM_HIP(hipMemcpy(t.fstart[d], h.fstart.data(), h.fstart.size() * sizeof(int32_t),
-                        hipMemcpyHostToDevice));
-    MFSEM_HIP(hipMemcpy(t.bidx[d], h.bidx.data(), h.bidx.size() * sizeof(int32_t),
-                        hipMemcpyHostToDevice));
-    upload(t.fcoef[d], h.fcoef, t.word);
-    upload(t.bcoef[d], h.bcoef, t.word);
-  }
 }
 
 void launch_box_parents_check(const int32_t n_fine[3], const int32_t* parent,
@@ -225,6 +252,15 @@ void launch_parents_range_check(int64_t n_fine, int64_t n_coarse, const int32_t*
 // x pass, y pass, z pass: (ncx, ncy, ncz) -> (nfx, ncy, ncz) -> (nfx, nfy, ncz)
 // -> (nfx, nfy, nfz)
 template <typename T>
+const ElemMat<T>& emat(const LatticeTransfer& t, int d);
+template <>
+const ElemMat<double>& emat<double>(const LatticeTransfer& t, int d) { return t.em64[d]; }
+template <>
+const ElemMat<float>& emat<float>(const LatticeTransfer& t, int d) { return t.em32[d]; }
+
+// x pass, y pass, z pass: (ncx, ncy, ncz) -> (nfx, ncy, ncz) -> (nfx, nfy, ncz)
+// -> (nfx, nfy, nfz)
+template <typename T>
 void lattice_prolong(const LatticeTransfer& t, int batch, const T* xc, T* xf, bool accumulate,
                      T* zero_f, hipStream_t s) {
   const LatticeAxisHost &hx = t.host[0], &hy = t.host[1], &hz = t.host[2];
@@ -232,28 +268,24 @@ void lattice_prolong(const LatticeTransfer& t, int batch, const T* xc, T* xf, bo
   T* s2 = static_cast<T*>(t.s2);
   {
     const int id[3] = {hx.nc, hy.nc, hz.nc}, od[3] = {hx.nf, hy.nc, hz.nc};
-    pass<T, 0, false, false, false>(xc, nullptr, s1, nullptr, od, id, t.fstart[0], t.fcoef[0],
-                                    hx.Wf, batch, s);
+    elem_pass<T, 0, false, false, false>(xc, nullptr, s1, nullptr, od, id, emat<T>(t, 0), batch, s);
   }
   {
     const int id[3] = {hx.nf, hy.nc, hz.nc}, od[3] = {hx.nf, hy.nf, hz.nc};
-    pass<T, 1, false, false, false>(s1, nullptr, s2, nullptr, od, id, t.fstart[1], t.fcoef[1],
-                                    hy.Wf, batch, s);
+    elem_pass<T, 1, false, false, false>(s1, nullptr, s2, nullptr, od, id, emat<T>(t, 1), batch, s);
   }
   {
     const int id[3] = {hx.nf, hy.nf, hz.nc}, od[3] = {hx.nf, hy.nf, hz.nf};
     if (accumulate)
-      pass<T, 2, false, false, true>(s2, nullptr, xf, zero_f, od, id, t.fstart[2], t.fcoef[2],
-                                     hz.Wf, batch, s);
+      elem_pass<T, 2, false, false, true>(s2, nullptr, xf, zero_f, od, id, emat<T>(t, 2), batch, s);
     else
-      pass<T, 2, false, false, false>(s2, nullptr, xf, zero_f, od, id, t.fstart[2], t.fcoef[2],
-                                      hz.Wf, batch, s);
+      elem_pass<T, 2, false, false, false>(s2, nullptr, xf, zero_f, od, id, emat<T>(t, 2), batch,
+                                           s);
   }
 }
 
-// transposed passes, z first so that the pass over the full fine lattice
-// reads its coefficient rows at a block-uniform coarse z:
-// (nfx, nfy, nfz) -> (nfx, nfy, ncz) -> (nfx, ncy, ncz) -> (ncx, ncy, ncz)
+// transposed passes, z first: (nfx, nfy, nfz) -> (nfx, nfy, ncz) -> (nfx, ncy, ncz)
+// -> (ncx, ncy, ncz)
 template <typename T>
 void lattice_restrict(const LatticeTransfer& t, int batch, const T* bf, const T* tf, T* rc,
                       hipStream_t s) {
@@ -263,21 +295,17 @@ void lattice_restrict(const LatticeTransfer& t, int batch, const T* bf, const T*
   {
     const int id[3] = {hx.nf, hy.nf, hz.nf}, od[3] = {hx.nf, hy.nf, hz.nc};
     if (tf)
-      pass<T, 2, true, true, false>(bf, tf, s2, nullptr, od, id, t.bidx[2], t.bcoef[2], hz.Wb,
-                                    batch, s);
+      elem_pass<T, 2, true, true, false>(bf, tf, s2, nullptr, od, id, emat<T>(t, 2), batch, s);
     else
-      pass<T, 2, true, false, false>(bf, nullptr, s2, nullptr, od, id, t.bidx[2], t.bcoef[2],
-                                     hz.Wb, batch, s);
+      elem_pass<T, 2, true, false, false>(bf, nullptr, s2, nullptr, od, id, emat<T>(t, 2), batch, s);
   }
   {
     const int id[3] = {hx.nf, hy.nf, hz.nc}, od[3] = {hx.nf, hy.nc, hz.nc};
-    pass<T, 1, true, false, false>(s2, nullptr, s1, nullptr, od, id, t.bidx[1], t.bcoef[1], hy.Wb,
-                                   batch, s);
+    elem_pass<T, 1, true, false, false>(s2, nullptr, s1, nullptr, od, id, emat<T>(t, 1), batch, s);
   }
   {
     const int id[3] = {hx.nf, hy.nc, hz.nc}, od[3] = {hx.nc, hy.nc, hz.nc};
-    pass<T, 0, true, false, false>(s1, nullptr, rc, nullptr, od, id, t.bidx[0], t.bcoef[0], hx.Wb,
-                                   batch, s);
+    elem_pass<T, 0, true, false, false>(s1, nullptr, rc, nullptr, od, id, emat<T>(t, 0), batch, s);
   }
 }
 

@@ -7,22 +7,25 @@
 
 namespace mfsem {
 
-// 1D transfer along one axis: fine node i takes sum_b fcoef[i][b] coarse[fstart[i] + b]
-// (Wf = Pc terms); the transpose, per coarse node o, is sum_k bcoef[o][k] fine[bidx[o][k]]
-// (Wb terms, zero-padded).
+// Node counts of the fine and coarse lattices along one axis.
 struct LatticeAxisHost {
-  int nf = 0, nc = 0;  // fine and coarse nodes along the axis
-  int Wf = 0, Wb = 0;
-  std::vector<int32_t> fstart, bidx;
-  std::vector<double> fcoef, bcoef;
+  int nf = 0, nc = 0;
+};
+
+// Dense 1D interpolation of one coarse element along an axis, [F+1][pc1]: row a
+// is the coarse basis at the a-th fine node of the element (F = p_f fine
+// intervals per coarse element for a p-transfer, 2p for an h-transfer), passed
+// to the element-block kernels by value.
+template <typename T>
+struct ElemMat {
+  int ne = 0, F = 0, pc1 = 0;  // coarse elements, fine intervals per element, coarse nodes per element
+  T M[(2 * MFSEM_MAX_P + 1) * (MFSEM_MAX_P + 1)] = {};
 };
 
 struct LatticeTransfer {
   LatticeAxisHost host[3];
-  int32_t* fstart[3] = {nullptr, nullptr, nullptr};
-  int32_t* bidx[3] = {nullptr, nullptr, nullptr};
-  void* fcoef[3] = {nullptr, nullptr, nullptr};
-  void* bcoef[3] = {nullptr, nullptr, nullptr};
+  ElemMat<double> em64[3];
+  ElemMat<float> em32[3];
   void* s1 = nullptr;  // intermediate lattices of the passes
   void* s2 = nullptr;
   size_t word = sizeof(double);
@@ -33,10 +36,10 @@ struct LatticeTransfer {
 // For h the parent/child arrays must also follow the box convention, which
 // the caller checks with launch_box_parents_check.
 bool lattice_transfer_applies(const mfsem_op& fine, const mfsem_op& coarse, int kind);
-// Carves tables and intermediates out of the arena (null pointers when sizing).
+// Builds the element matrices and carves the intermediate lattices out of the
+// arena (null pointers when sizing).
 void lattice_transfer_layout(LatticeTransfer& t, const mfsem_op& fine, const mfsem_op& coarse,
                              int kind, int batch, size_t word, Arena& a);
-void lattice_transfer_upload(const LatticeTransfer& t);
 // Adds to *mismatch the fine elements whose parent/child differ from the box
 // convention (parent = the element of (ex/2, ey/2, ez/2) on the coarse lattice,
 // child bits = ex & 1, ey & 1, ez & 1).
