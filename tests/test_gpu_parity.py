@@ -530,6 +530,30 @@ def test_batched_pcg_and_grad():
         assert rel_l2(g, g_ref) <= TOL64
 
 
+def test_c4_shaped_batch8_solve_and_grad():
+    """The c4 workload's shape at reduced size: a p = 4 box at the c4 element
+    edge (0.5 mm) with the c4 fiber, 8 per-element conductivity sets drawn as
+    in c4, one batched GMG-PCG solve of all 8 and the dL/dsigma contraction of
+    all 8 in one launch, each member against the oracle (1e-12)."""
+    announce("c4-shaped batch 8")
+    spec = synth.C4.with_(n=(3, 3, 2), length=(1.5, 1.5, 1.0))
+    B = 8
+    sig = synth.element_sigma(4, B, spec.n_elem)
+    ops, mg = mf.hierarchy(spec, coarsening=(("p", 2), ("p", 1)), degree=3, sigma=to_dev(sig))
+    f = synth.uniform(5, (B, spec.n_dof))
+    x, info = mf.pcg(ops[0], to_dev(f), mg=mg, rtol=1e-14, max_it=300)
+    assert info.status == [0] * B
+    u = synth.uniform(6, (B, spec.n_dof))
+    w = synth.uniform(7, (B, spec.n_dof))
+    g = to_np(ops[0].grad_sigma(to_dev(u), to_dev(w)))
+    xs = to_np(x)
+    for b in range(B):
+        prob = oop.Problem(spec, sigma=sig[b])
+        A, _, _ = prob.assemble()
+        assert rel_l2(xs[b], spla.spsolve(A.tocsc(), f[b])) <= TOL64, b
+        assert rel_l2(g[b], oadj.grad_sigma(prob, u[b], w[b])) <= TOL64, b
+
+
 GRAD_CASES = {
     "fiber-p3": synth.BoxSpec(p=3, n=(3, 2, 2), length=(1.5, 1.0, 1.0), fiber=True, theta0=-1.0,
                               theta1=1.0, sigma=(0.17, 0.03, 0.03), alpha=2.0),
