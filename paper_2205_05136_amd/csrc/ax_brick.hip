@@ -16,7 +16,7 @@
 //   5. each lattice node of the brick is added into y with one global atomic.
 // Compared with one gather and one scatter-add per element node, global reads of
 // x and atomics drop from NE (p+1)^3 to (BX p+1)(BY p+1)(BZ p+1) per brick
-// (1000 -> 825 for the 8 x 1 x 1 bricks at p = 4), and no index array is read.
+// (1250 -> 1025 for the 10 x 1 x 1 bricks at p = 4), and no index array is read.
 // On small meshes (a few thousand elements) one- and two-element bricks, which give the grid
 // more waves, measured slower than these shapes: the extra global atomics on
 // shared nodes cost more than the added parallelism gains.
@@ -33,16 +33,22 @@ constexpr int r64(int n) { return ((n + 63) / 64) * 64; }
 // waves per SIMD the register budget must allow (VGPRs <= 512/W).  Bricks are
 // long along x, the fastest index of both the node lattice and the element
 // order: the lattice rows a brick gathers are longer runs of consecutive nodes
-// and its elements' G values are one contiguous run per (y, z) row.  Measured on
-// the 51M-DOF slab against the cube-like shapes (2x2x2 at p = 4, 2x2x1 at
-// p = 5..7, 4x2x2 at p = 3, 4x4x2 at p = 2): FP64 1-7% and FP32 3-12% faster.
+// and its elements' G values are one contiguous run per (y, z) row (measured on
+// the 51M-DOF slab against cube-like shapes: FP64 1-7% and FP32 3-12% faster).
+// Their length keeps a workgroup near 256 lanes, so that several workgroups fit
+// a CU at the register-limited occupancy: at p = 4 a 16-element brick (400
+// lanes, 7 waves) left one workgroup per CU at 3 waves per SIMD, the 10-element
+// brick (250 lanes) three; likewise 28 elements at p = 2 (against 32 x 2), 7 at
+// p = 5 (against 8) and 5 at p = 6 (against 4, 196 lanes in 4 waves).  Measured
+// FP64 on the 51M-DOF slab: p = 2 2.13 -> 1.92 ms, p = 4 1.30 -> 1.27 ms,
+// p = 5 1.16 -> 1.14 ms, p = 6 1.23 -> 1.12 ms.
 template <int P> struct BrickShape;
 template <> struct BrickShape<2> { static constexpr int X = 32, Y = 2, Z = 1, W = 4; };
-template <> struct BrickShape<3> { static constexpr int X = 16, Y = 2, Z = 1, W = 4; };
+template <> struct BrickShape<3> { static constexpr int X = 28, Y = 1, Z = 1, W = 4; };
 template <> struct BrickShape<4> { static constexpr int X = 16, Y = 1, Z = 1, W = 3; };
-template <> struct BrickShape<5> { static constexpr int X = 8, Y = 1, Z = 1, W = 3; };
-template <> struct BrickShape<6> { static constexpr int X = 4, Y = 1, Z = 1, W = 3; };
-template <> struct BrickShape<7> { static constexpr int X = 4, Y = 1, Z = 1, W = 2; };
+template <> struct BrickShape<5> { static constexpr int X = 10, Y = 1, Z = 1, W = 3; };
+template <> struct BrickShape<6> { static constexpr int X = 7, Y = 1, Z = 1, W = 3; };
+template <> struct BrickShape<7> { static constexpr int X = 5, Y = 1, Z = 1, W = 2; };
 template <> struct BrickShape<8> { static constexpr int X = 2, Y = 1, Z = 2, W = 2; };
 template <> struct BrickShape<9> { static constexpr int X = 2, Y = 1, Z = 1, W = 2; };
 
