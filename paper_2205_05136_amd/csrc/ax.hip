@@ -20,6 +20,7 @@
 // sum is a hardware FP64/FP32 atomic add; y must be zero (or hold what is to be
 // added to) beforehand.
 #include "internal.hpp"
+#include "rules.hpp"
 
 namespace mfsem {
 
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
   T ur[P], us[P], ut[P];
   if (active) {
     // this lane's rows of the 1D derivative matrix in registers; the
-    // lane-uniform entries of the third direction from scalar loads
+    // lane-uniform entries of the third direction are compile-time constants
     T dx[P], dy[P];
 #pragma unroll
     for (int m = 0; m < P; ++m) {
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
       for (int m = 0; m < P; ++m) {
         r += dx[m] * su[c * P2 + ib * P + m];
         s += dy[m] * su[c * P2 + m * P + ia];
-        t += Dtab[c * P + m] * u[m];
+        t += T(rules::GllTables<P>::D.v[c * P + m]) * u[m];
       }
       ur[c] = r;
       us[c] = s;
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(NiCfg<P>::THREADS) void ax_ni_kernel(
       for (int m = 0; m < P; ++m) {
         v += dxt[m] * su[c * P2 + ib * P + m];
         v += dyt[m] * sv[c * P2 + m * P + ia];
-        v += Dtab[m * P + c] * ft[m];
+        v += T(rules::GllTables<P>::D.v[m * P + c]) * ft[m];
       }
       atomic_add(&y[gi[c]], v);
     }
@@ -178,9 +179,9 @@ struct SemCfg {
 };
 
 // Waves per SIMD the register budget must allow: 3 for the FP64 kernels from
-// P = 6 with up to 9 Gauss points (at P = 8, Q = 9: 168 VGPRs with 24 B/lane
-// spilled, against 183 VGPRs and 2 waves unconstrained; the LDS of three
-// 3-element workgroups fits a CU).
+// P = 6 with up to 9 Gauss points (at P = 8, Q = 9: 168 VGPRs and no spill,
+// against 178 VGPRs and 2 waves unconstrained; the LDS of three 3-element
+// workgroups fits a CU).
 template <typename T, int P, int Q>
 constexpr int sem_min_waves() { return (sizeof(T) == 8 && P >= 6 && Q <= 9) ? 3 : 1; }
 
@@ -192,6 +193,8 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
     T* __restrict__ y) {
   using C = SemCfg<P, Q>;
   constexpr int P2 = C::P2, P3 = C::P3, Q2 = C::Q2, Q3 = C::Q3, NE = C::NE;
+  // lane-uniform entries (z direction) are compile-time constants
+  using R = rules::SemTables<P, Q>;
   __shared__ T sB[Q * P];
   __shared__ T sDq[Q * Q];
   __shared__ T s1[NE * C::L1];
@@ -249,7 +252,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
     for (int k = 0; k < Q; ++k) {
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < P; ++c) s += Btab[k * P + c] * b1[c * Q2 + j * Q + i];
+      for (int c = 0; c < P; ++c) s += T(R::B.v[k * P + c]) * b1[c * Q2 + j * Q + i];
       b3[k * Q2 + j * Q + i] = s;
     }
   }
@@ -266,7 +269,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
         for (int m = 0; m < Q; ++m) {
           sx += sDq[i * Q + m] * b3[k * Q2 + j * Q + m];
           sy += sDq[j * Q + m] * b3[k * Q2 + m * Q + i];
-          sz += Dqtab[k * Q + m] * b3[m * Q2 + j * Q + i];
+          sz += T(R::Dq.v[k * Q + m]) * b3[m * Q2 + j * Q + i];
         }
         dx[k] = sx;
         dy[k] = sy;
@@ -312,7 +315,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
         for (int m = 0; m < Q; ++m) {
           v += sDq[m * Q + i] * b3[k * Q2 + j * Q + m];
           v += sDq[m * Q + j] * b2[k * Q2 + m * Q + i];
-          v += Dqtab[m * Q + k] * fz[m];
+          v += T(R::Dq.v[m * Q + k]) * fz[m];
         }
         rq[k] = v;
       }
@@ -330,7 +333,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
     for (int c = 0; c < P; ++c) {
       T s = 0;
 #pragma unroll
-      for (int k = 0; k < Q; ++k) s += Btab[k * P + c] * rq[k];
+      for (int k = 0; k < Q; ++k) s += T(R::B.v[k * P + c]) * rq[k];
       b1[c * Q2 + j * Q + i] = s;
     }
   }

@@ -21,6 +21,7 @@
 // more waves, measured slower than these shapes: the extra global atomics on
 // shared nodes cost more than the added parallelism gains.
 #include "internal.hpp"
+#include "rules.hpp"
 
 namespace mfsem {
 
@@ -84,7 +85,7 @@ __device__ inline void lds_add(T* p, T v) {
 // coordinates cs [3][LN]; xk holds the coordinates along the pencil.
 template <typename T, int P, int LX, int LY, int LN>
 __device__ inline void otf_point(const T* cs, int o, int ia, int ib, int c, const T (&dx)[P],
-                                 const T (&dy)[P], const T* Dtab, const T (&xk)[3][P],
+                                 const T (&dy)[P], const T (&xk)[3][P],
                                  const T (&f)[3], bool has_fiber, T sl, T st, T W, T (&g)[6],
                                  T& wj) {
   T J[3][3];  // J[r][d] = d X_r / d xi_d
@@ -95,7 +96,7 @@ __device__ inline void otf_point(const T* cs, int o, int ia, int ib, int c, cons
     for (int m = 0; m < P; ++m) {
       a0 += dx[m] * cs[r * LN + o - ia + m + LX * LY * c];
       a1 += dy[m] * cs[r * LN + o - LX * ib + LX * m + LX * LY * c];
-      a2 += Dtab[c * P + m] * xk[r][m];
+      a2 += T(rules::GllTables<P>::D.v[c * P + m]) * xk[r][m];
     }
     J[r][0] = a0;
     J[r][1] = a1;
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
   __syncthreads();
 
   // this lane's rows of the 1D derivative matrix stay in registers; the
-  // lane-uniform entries of the third direction come from scalar loads
+  // lane-uniform entries of the third direction are compile-time constants
   T dx[P], dy[P];
 #pragma unroll
   for (int m = 0; m < P; ++m) {
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       T wjo = 0;
-      if constexpr (OTF) otf_point<T, P, LX, LY, LN>(cs, o, ia, ib, c, dx, dy, Dtab, xk, fv[c],
+      if constexpr (OTF) otf_point<T, P, LX, LY, LN>(cs, o, ia, ib, c, dx, dy, xk, fv[c],
                                                     fiber != nullptr, sl, st, wab * sw[c], g[c], wjo);
       const T g00 = g[c][0], g01 = g[c][1], g02 = g[c][2];
       const T g11 = g[c][3], g12 = g[c][4], g22 = g[c][5];
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
       for (int m = 0; m < P; ++m) {
         r += dx[m] * xs[o - ia + m + LX * LY * c];
         s += dy[m] * xs[o - LX * ib + LX * m + LX * LY * c];
-        t += Dtab[c * P + m] * u[m];
+        t += T(rules::GllTables<P>::D.v[c * P + m]) * u[m];
       }
       const int q = c * P2 + ab;
       Fe[q] = g00 * r + g01 * s + g02 * t;
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
       for (int m = 0; m < P; ++m) {
         v += dxt[m] * Fe[c * P2 + ib * P + m];
         v += dyt[m] * Fe[P3 + c * P2 + m * P + ia];
-        v += Dtab[m * P + c] * ft[m];
+        v += T(rules::GllTables<P>::D.v[m * P + c]) * ft[m];
       }
       if constexpr (GATHER) out[c] = v;
       else lds_add(&ys[o + LX * LY * c], v);
