@@ -272,6 +272,17 @@ unsigned grid_for(int64_t n) {
   return (unsigned)b;
 }
 
+// grid of the streaming kernels that write T: FP32 vectors need more lanes in
+// flight than FP64 ones to keep the same bytes outstanding
+template <typename T>
+unsigned stream_grid(int64_t n) {
+  constexpr int64_t cap = sizeof(T) <= 4 ? 4096 : 1024;
+  int64_t b = (n + VT - 1) / VT;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
 }  // namespace
 
 int dot_blocks(int64_t n) { return (int)grid_for(n); }
@@ -279,14 +290,14 @@ int dot_blocks(int64_t n) { return (int)grid_for(n); }
 template <typename T>
 void vfill(T* x, int64_t n, T v, hipStream_t s) {
   if (n <= 0) return;
-  fill_kernel<T><<<grid_for(n), VT, 0, s>>>(x, n, v);
+  fill_kernel<T><<<stream_grid<T>(n), VT, 0, s>>>(x, n, v);
   MFSEM_LAUNCH("fill_kernel");
 }
 
 template <typename A, typename B>
 void vcast(const A* x, B* y, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  cast_kernel<A, B><<<grid_for(n), VT, 0, s>>>(x, y, n);
+  cast_kernel<A, B><<<stream_grid<B>(n), VT, 0, s>>>(x, y, n);
   MFSEM_LAUNCH("cast_kernel");
 }
 
@@ -328,33 +339,33 @@ template <typename T>
 void vjacobi(T* x, T* b, T* t, const T* dinv, int64_t n, int batch, const double* coef,
              bool overwrite, bool clear_t, bool clear_b, hipStream_t s) {
   const int flags = (overwrite ? 1 : 0) | (clear_t ? 2 : 0) | (clear_b ? 4 : 0);
-  jacobi_kernel<T><<<dim3(grid_for(n), batch), VT, 0, s>>>(x, b, t, dinv, n, coef, flags);
+  jacobi_kernel<T><<<dim3(stream_grid<T>(n), batch), VT, 0, s>>>(x, b, t, dinv, n, coef, flags);
   MFSEM_LAUNCH("jacobi_kernel");
 }
 
 template <typename T>
 void vaxpy(T* y, T* x, int64_t n, bool clear_x, hipStream_t s) {
   if (n <= 0) return;
-  axpy_kernel<T><<<grid_for(n), VT, 0, s>>>(y, x, n, clear_x ? 1 : 0);
+  axpy_kernel<T><<<stream_grid<T>(n), VT, 0, s>>>(y, x, n, clear_x ? 1 : 0);
   MFSEM_LAUNCH("axpy_kernel");
 }
 
 template <typename T>
 void vinvert(T* x, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  invert_kernel<T><<<grid_for(n), VT, 0, s>>>(x, n);
+  invert_kernel<T><<<stream_grid<T>(n), VT, 0, s>>>(x, n);
   MFSEM_LAUNCH("invert_kernel");
 }
 
 template <typename T>
 void vlin(T* y, const T* x, int64_t n, int batch, const double* c, hipStream_t s) {
-  lin_kernel<T><<<dim3(grid_for(n), batch), VT, 0, s>>>(y, x, n, c);
+  lin_kernel<T><<<dim3(stream_grid<T>(n), batch), VT, 0, s>>>(y, x, n, c);
   MFSEM_LAUNCH("lin_kernel");
 }
 
 template <typename T>
 void vmul(T* z, const T* w, const T* r, int64_t n, int batch, hipStream_t s) {
-  mul_kernel<T><<<dim3(grid_for(n), batch), VT, 0, s>>>(z, w, r, n);
+  mul_kernel<T><<<dim3(stream_grid<T>(n), batch), VT, 0, s>>>(z, w, r, n);
   MFSEM_LAUNCH("mul_kernel");
 }
 
