@@ -284,27 +284,34 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
       // stream; wtab holds w and then 1/w^2), else the stored W|J|
       const T id = idet ? idet[(int64_t)bt * n_elem + e] : T(0);
       const T iw2ij = idet ? wtab[Q + i] * wtab[Q + j] : T(0);
+      // one branch-free loop per mass source, so that the G loads of later
+      // planes can be issued ahead of the earlier planes' arithmetic
+      auto flux = [&](auto det_tag) {
+        constexpr bool DET = decltype(det_tag)::value;
 #pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        const int q = k * Q2 + j * Q + i;
-        T g6[6];
-        load_g6(Ge + (int64_t)q * 6, g6);
-        const T g00 = g6[0], g01 = g6[1], g02 = g6[2];
-        const T g11 = g6[3], g12 = g6[4], g22 = g6[5];
-        const T uk = b3[q];  // this lane's value, read before its flux overwrites it
-        b3[q] = g00 * dx[k] + g01 * dy[k] + g02 * dz[k];
-        b2[q] = g01 * dx[k] + g11 * dy[k] + g12 * dz[k];
-        fz[k] = g02 * dx[k] + g12 * dy[k] + g22 * dz[k];
-        T wj;
-        if (idet) {
-          const T dG = g00 * (g11 * g22 - g12 * g12) - g01 * (g01 * g22 - g12 * g02) +
-                       g02 * (g01 * g12 - g11 * g02);
-          wj = dG * (id * iw2ij) * wtab[Q + k];
-        } else {
-          wj = WJ[e * Q3 + q];
+        for (int k = 0; k < Q; ++k) {
+          const int q = k * Q2 + j * Q + i;
+          T g6[6];
+          load_g6(Ge + (int64_t)q * 6, g6);
+          const T g00 = g6[0], g01 = g6[1], g02 = g6[2];
+          const T g11 = g6[3], g12 = g6[4], g22 = g6[5];
+          const T uk = b3[q];  // this lane's value, read before its flux overwrites it
+          b3[q] = g00 * dx[k] + g01 * dy[k] + g02 * dz[k];
+          b2[q] = g01 * dx[k] + g11 * dy[k] + g12 * dz[k];
+          fz[k] = g02 * dx[k] + g12 * dy[k] + g22 * dz[k];
+          T wj;
+          if constexpr (DET) {
+            const T dG = g00 * (g11 * g22 - g12 * g12) - g01 * (g01 * g22 - g12 * g02) +
+                         g02 * (g01 * g12 - g11 * g02);
+            wj = dG * (id * iw2ij) * T(R::iw2.v[k]);
+          } else {
+            wj = WJ[e * Q3 + q];
+          }
+          rq[k] = alpha * wj * uk;
         }
-        rq[k] = alpha * wj * uk;
-      }
+      };
+      if (idet) flux(std::true_type{});
+      else flux(std::false_type{});
     }
     __syncthreads();
     if (active) {

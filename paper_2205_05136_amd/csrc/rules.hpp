@@ -78,6 +78,20 @@ constexpr Vec<Q> gauss_points() {
   return r;
 }
 
+// 1 / w_k^2 for the Q-point Gauss weights w = 2 / ((1 - x^2) P_Q'(x)^2)
+template <int Q>
+constexpr Vec<Q> gauss_inverse_square_weights() {
+  const Vec<Q> x = gauss_points<Q>();
+  Vec<Q> r{};
+  for (int i = 0; i < Q; ++i) {
+    double Pn = 0, dPn = 0;
+    legendre(Q, x.v[i], Pn, dPn);
+    const double w = 2.0 / ((1.0 - x.v[i] * x.v[i]) * dPn * dPn);
+    r.v[i] = 1.0 / (w * w);
+  }
+  return r;
+}
+
 // the P = p + 1 GLL nodes
 template <int P>
 constexpr Vec<P> gll_points() {
@@ -142,15 +156,16 @@ struct GllTables {
   static constexpr Vec<P * P> D = lagrange_derivatives<P, P>(nodes, nodes);
 };
 
-// SEM: B[k][a] = l_a(x_k) from the P GLL nodes to the Q Gauss points, and the
+// SEM: B[k][a] = l_a(x_k) from the P GLL nodes to the Q Gauss points, the
 // collocation derivative Dq[k][m] = L_m'(x_k) of the Lagrange basis on the
-// Gauss points (the run-time tables B and Dq)
+// Gauss points, and 1/w_k^2 (the run-time tables B, Dq and iw2)
 template <int P, int Q>
 struct SemTables {
   static constexpr Vec<P> nodes = gll_points<P>();
   static constexpr Vec<Q> points = gauss_points<Q>();
   static constexpr Vec<Q * P> B = lagrange_values<P, Q>(nodes, points);
   static constexpr Vec<Q * Q> Dq = lagrange_derivatives<Q, Q>(points, points);
+  static constexpr Vec<Q> iw2 = gauss_inverse_square_weights<Q>();
 };
 
 }  // namespace rules

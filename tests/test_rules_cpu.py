@@ -1,5 +1,5 @@
 """The compile-time 1D tables of the apply kernels (csrc/rules.hpp) against the
-oracle's quadrature rules and Lagrange matrices (Section 3: GLL nodes carry the
+oracle's quadrature rules, weights and Lagrange matrices (Section 3: GLL nodes carry the
 basis; SEM-NI integrates on them, SEM on Legendre-Gauss points).
 
 The header is plain C++17, so it is compiled here with the host compiler and
@@ -32,6 +32,7 @@ def _program():
     for P, Q in SEM_PQ:
         lines.append(f"  put(\"B\", {P}, {Q}, SemTables<{P}, {Q}>::B);")
         lines.append(f"  put(\"Dq\", {P}, {Q}, SemTables<{P}, {Q}>::Dq);")
+        lines.append(f"  put(\"iw2\", {P}, {Q}, SemTables<{P}, {Q}>::iw2);")
     lines += ["  return 0;", "}"]
     return "\n".join(lines) + "\n"
 
@@ -69,3 +70,9 @@ def test_sem_interpolation_and_collocation_derivative(tables, P, Q):
     xq, _ = gauss(Q)
     assert _close(tables[("B", P, Q)], lagrange(xn, xq).ravel())
     assert _close(tables[("Dq", P, Q)], lagrange_deriv(xq, xq).ravel())
+
+
+@pytest.mark.parametrize("P,Q", SEM_PQ)
+def test_sem_inverse_square_gauss_weights(tables, P, Q):
+    _, w = gauss(Q)
+    assert _close(tables[("iw2", P, Q)], 1.0 / w ** 2)
