@@ -284,10 +284,13 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
       // stream; wtab holds w and then 1/w^2), else the stored W|J|
       const T id = idet ? idet[(int64_t)bt * n_elem + e] : T(0);
       const T iw2ij = idet ? wtab[Q + i] * wtab[Q + j] : T(0);
-      // one branch-free loop per mass source, so that the G loads of later
-      // planes can be issued ahead of the earlier planes' arithmetic
-      auto flux = [&](auto det_tag) {
-        constexpr bool DET = decltype(det_tag)::value;
+      // one branch-free loop per mass source (MASS 1: W|J| from det G, 0: the
+      // stored W|J|), so that the G loads of later planes are issued ahead of
+      // the earlier planes' arithmetic; FP64 with P <= 4 keeps the choice in
+      // the loop (MASS -1): there the hoisted loads cost a wave per SIMD
+      // (p = 2, q = 4: 4.6 -> 5.8 ms on the 51M-DOF slab)
+      auto flux = [&](auto mass_tag) {
+        constexpr int MASS = decltype(mass_tag)::value;
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
           const int q = k * Q2 + j * Q + i;
@@ -300,7 +303,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
           b2[q] = g01 * dx[k] + g11 * dy[k] + g12 * dz[k];
           fz[k] = g02 * dx[k] + g12 * dy[k] + g22 * dz[k];
           T wj;
-          if constexpr (DET) {
+          if (MASS == 1 || (MASS == -1 && idet)) {
             const T dG = g00 * (g11 * g22 - g12 * g12) - g01 * (g01 * g22 - g12 * g02) +
                          g02 * (g01 * g12 - g11 * g02);
             wj = dG * (id * iw2ij) * T(R::iw2.v[k]);
@@ -310,8 +313,9 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
           rq[k] = alpha * wj * uk;
         }
       };
-      if (idet) flux(std::true_type{});
-      else flux(std::false_type{});
+      if constexpr (sizeof(T) == 8 && P <= 4) flux(std::integral_constant<int, -1>{});
+      else if (idet) flux(std::integral_constant<int, 1>{});
+      else flux(std::integral_constant<int, 0>{});
     }
     __syncthreads();
     if (active) {
