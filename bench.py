@@ -799,11 +799,18 @@ def main():
                              "V_range_mV": [round(float(sim.V.min()), 3), round(float(sim.V.max()), 3)],
                              "sim_time_ms": round(sim.t, 4), "setup_s": round(t_setup, 3),
                              "scheme": sim.scheme}
-        act = sim.act[sim.act >= 0]
+        # every node has a largest |dV/dt| once a step has run; it marks an
+        # activation only where the node depolarised, i.e. where that rate is an
+        # upstroke's (above 10 mV/ms; resting tissue ahead of the front changes
+        # orders of magnitude more slowly)
+        up = (sim.act >= 0) & (sim.act_rate > 10.0)
+        act = sim.act[up]
         out["monodomain"]["activated_fraction"] = round(act.numel() / sim.act.numel(), 5)
         out["monodomain"]["activation_ms_range"] = (
             [round(float(act.min()), 4), round(float(act.max()), 4)] if act.numel() else None)
-        out["monodomain"]["activation"] = "time of the largest |dV/dt| per node (step midpoint)"
+        out["monodomain"]["max_rate_mV_per_ms"] = round(float(sim.act_rate.max()), 3)
+        out["monodomain"]["activation"] = ("time of the largest |dV/dt| per node (step midpoint), "
+                                           "counted where that rate exceeds 10 mV/ms")
     if kind == "pcg" and not args.no_matrix_based:
         out["matrix_based"] = matrix_based(mf, op, x, t_kernel, spec)
     if args.copy_ref:
