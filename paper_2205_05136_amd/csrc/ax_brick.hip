@@ -53,6 +53,16 @@ template <> struct BrickShape<7> { static constexpr int X = 5, Y = 1, Z = 1, W =
 template <> struct BrickShape<8> { static constexpr int X = 2, Y = 1, Z = 2, W = 2; };
 template <> struct BrickShape<9> { static constexpr int X = 2, Y = 1, Z = 1, W = 2; };
 
+// Loads in the order the kernel needs them (see the kernel), chosen per
+// precision and degree by measurement on the 51M-DOF slab: FP64 p = 3 / 4 / 5
+// 1.454 -> 1.448, 1.268 -> 1.237, 1.145 -> 1.128 ms, FP32 p = 5 / 6 / 7 0.585 ->
+// 0.579, 0.549 -> 0.544, 0.558 -> 0.540 ms; slower at FP64 p = 2 (1.915 -> 1.930)
+// and p = 7 (1.090 -> 1.136 ms), even at FP64 p = 6.
+template <typename T, int P>
+constexpr bool brick_ordered_loads() {
+  return sizeof(T) == 8 ? (P >= 4 && P <= 6) : (P >= 6);
+}
+
 template <int P>
 struct BrickCfg {
   static constexpr int p = P - 1, P2 = P * P, P3 = P2 * P;
@@ -186,15 +196,32 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
   // 1. issue every global load before any LDS traffic, so they are all in
   // flight together: the lattice values of x and the six G values of each of
   // the pencil's P points (the dominant HBM stream)
+  // With ORD every load is issued unconditionally (out-of-range lanes read a
+  // valid address and discard the value) and in the order the kernel needs
+  // them: the small tables, the lattice of x, 1/det sigma, then G.  No load is
+  // skipped on any path, so the wait before the LDS writes covers the tables and
+  // x only and G stays in flight through the barrier and the first derivatives;
+  // without ORD the table loads come last and that wait covers G too.
+  constexpr bool ORD = brick_ordered_loads<T, P>();
+  static_assert(!ORD || (C::THREADS >= P * P && C::THREADS >= 2 * P), "one table entry per lane");
+  T dtv = 0, wtv = 0;
+  if constexpr (ORD) {
+    dtv = Dtab[tid < P * P ? tid : 0];
+    wtv = wtab[tid < 2 * P ? tid : 0];
+  }
   constexpr int NIT = (LN + C::THREADS - 1) / C::THREADS;
   T xv[NIT];
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int n = tid + it * C::THREADS;
     const int i = n % LX, j = (n / LX) % LY, k = n / (LX * LY);
-    xv[it] = (n < LN && i <= nex * p && j <= ney * p && k <= nez * p)
-                 ? x[(I0 + i) + NX * ((J0 + j) + NY * (K0 + k))]
-                 : T(0);
+    const bool in = n < LN && i <= nex * p && j <= ney * p && k <= nez * p;
+    if constexpr (ORD) {
+      const T v = x[in ? (I0 + i) + NX * ((J0 + j) + NY * (K0 + k)) : 0];
+      xv[it] = in ? v : T(0);
+    } else {
+      xv[it] = in ? x[(I0 + i) + NX * ((J0 + j) + NY * (K0 + k))] : T(0);
+    }
   }
   T g[P][6];
   T id = 0;
@@ -227,14 +254,26 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
         st = s_t;
       }
     }
+  } else if constexpr (ORD) {
+    const int64_t ec = active ? e : 0;
+    const T iv = (idet ? idet : G)[(int64_t)bt * ne_tot + ec];
+    const T* Ge = G + (((int64_t)bt * ne_tot + ec) * P3 + ab) * 6;
+#pragma unroll
+    for (int c = 0; c < P; ++c) load_g6(Ge + c * P2 * 6, g[c]);
+    id = idet ? iv : T(0);
   } else if (active) {
     const T* Ge = G + (((int64_t)bt * ne_tot + e) * P3 + ab) * 6;
 #pragma unroll
     for (int c = 0; c < P; ++c) load_g6(Ge + c * P2 * 6, g[c]);
     if (idet) id = idet[(int64_t)bt * ne_tot + e];
   }
-  for (int i = tid; i < P * P; i += C::THREADS) sD[i] = Dtab[i];
-  for (int i = tid; i < 2 * P; i += C::THREADS) sw[i] = wtab[i];
+  if constexpr (ORD) {
+    if (tid < P * P) sD[tid] = dtv;
+    if (tid < 2 * P) sw[tid] = wtv;
+  } else {
+    for (int i = tid; i < P * P; i += C::THREADS) sD[i] = Dtab[i];
+    for (int i = tid; i < 2 * P; i += C::THREADS) sw[i] = wtab[i];
+  }
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int n = tid + it * C::THREADS;
