@@ -229,6 +229,26 @@ def test_apply_batch_sigma():
     assert rel_l2(y2[0], A0 @ x[0]) <= TOL64
 
 
+@pytest.mark.parametrize("p,n", [(5, (9, 2, 2)), (6, (8, 1, 2)), (7, (3, 1, 3))])
+def test_apply_batch_ragged_bricks_f64_f32(p, n):
+    """Batched applies (two sigma sets) on meshes whose last lattice brick is
+    partial along x and z, in FP64 and FP32, so that the lanes outside the mesh
+    (which load from a clamped address and discard the value) are exercised in
+    both load orders of the lattice kernel."""
+    announce(f"apply batch 2 ragged bricks p={p} n={n}")
+    spec = _spec(p, n)
+    sig = synth.element_sigma(41 + p, 2, spec.n_elem)
+    op = mf.Operator.from_spec(spec, sigma=to_dev(sig), store_f32=True)
+    x = synth.uniform(103 + p, (2, spec.n_dof))
+    y64 = to_np(op.apply(to_dev(x)))
+    y32 = to_np(op.apply(to_dev(x, torch.float32)))
+    for b in range(2):
+        A, _, _ = oop.Problem(spec, sigma=sig[b]).assemble()
+        ref = A @ x[b]
+        assert rel_l2(y64[b], ref) <= TOL64, b
+        assert rel_l2(y32[b], ref) <= TOL32, b
+
+
 def test_apply_sheet_orthotropic():
     """Full orthotropic tensor with a sheet field (sigma_n != sigma_t)."""
     announce("apply orthotropic sheet")
