@@ -58,6 +58,14 @@ template <> struct BrickShape<9> { static constexpr int X = 2, Y = 1, Z = 1, W =
 // 1.454 -> 1.448, 1.268 -> 1.237, 1.145 -> 1.128 ms, FP32 p = 5 / 6 / 7 0.585 ->
 // 0.579, 0.549 -> 0.544, 0.558 -> 0.540 ms; slower at FP64 p = 2 (1.915 -> 1.930)
 // and p = 7 (1.090 -> 1.136 ms), even at FP64 p = 6.
+// z-rows of bricks per tile of the brick order (see the kernel), by measurement
+// on the 51M-DOF slab: p = 7 (2 x 1 x 2 bricks) FP64 1.122 -> 1.063 ms with 4;
+// p = 2 and 4 were slower with any tile (p = 4: 1.225 -> 1.242..1.268 ms).
+template <int P>
+constexpr int brick_z_tile() {
+  return P == 8 ? 4 : 1;
+}
+
 template <typename T, int P>
 constexpr bool brick_ordered_loads() {
   return sizeof(T) == 8 ? (P >= 4 && P <= 6) : (P >= 6);
@@ -173,9 +181,24 @@ __global__ __launch_bounds__(BrickCfg<P>::THREADS,
   __shared__ T cs[OTF ? 3 * LN : 1];  // OTF: lattice coordinates [3][LN]
 
   const int tid = threadIdx.x;
-  const int nbx = (nx + BX - 1) / BX, nby = (ny + BY - 1) / BY;
+  const int nbx = (nx + BX - 1) / BX, nby = (ny + BY - 1) / BY, nbz = (nz + BZ - 1) / BZ;
   const int brick = (int)xcd_block(blockIdx.x, gridDim.x);
-  const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
+  // brick order: x fastest, then y, then z; with TZ > 1 the rows of bricks go
+  // through tiles of TZ z-rows (z fastest within a tile, then y), so that
+  // bricks sharing a z-face run close together in time on one XCD
+  constexpr int TZ = brick_z_tile<P>();
+  int bxi, byi, bzi;
+  if constexpr (TZ == 1) {
+    bxi = brick % nbx;
+    byi = (brick / nbx) % nby;
+    bzi = brick / (nbx * nby);
+  } else {
+    const int row = brick / nbx, ztile = row / (nby * TZ), rem = row - ztile * nby * TZ;
+    const int nzt = min(TZ, nbz - ztile * TZ);
+    bxi = brick % nbx;
+    byi = rem / nzt;
+    bzi = ztile * TZ + rem % nzt;
+  }
   const int ex0 = bxi * BX, ey0 = byi * BY, ez0 = bzi * BZ;
   const int nex = min(BX, nx - ex0), ney = min(BY, ny - ey0), nez = min(BZ, nz - ez0);
   const int64_t NX = (int64_t)p * nx + 1, NY = (int64_t)p * ny + 1;
