@@ -53,11 +53,6 @@ template <> struct BrickShape<7> { static constexpr int X = 5, Y = 1, Z = 1, W =
 template <> struct BrickShape<8> { static constexpr int X = 2, Y = 1, Z = 2, W = 2; };
 template <> struct BrickShape<9> { static constexpr int X = 2, Y = 1, Z = 1, W = 2; };
 
-// Loads in the order the kernel needs them (see the kernel), chosen per
-// precision and degree by measurement on the 51M-DOF slab: FP64 p = 3 / 4 / 5
-// 1.454 -> 1.448, 1.268 -> 1.237, 1.145 -> 1.128 ms, FP32 p = 5 / 6 / 7 0.585 ->
-// 0.579, 0.549 -> 0.544, 0.558 -> 0.540 ms; slower at FP64 p = 2 (1.915 -> 1.930)
-// and p = 7 (1.090 -> 1.136 ms), even at FP64 p = 6.
 // z-rows of bricks per tile of the brick order (see the kernel), by measurement
 // on the 51M-DOF slab: p = 7 (2 x 1 x 2 bricks) FP64 1.122 -> 1.063 ms with 4;
 // p = 2 and 4 were slower with any tile (p = 4: 1.225 -> 1.242..1.268 ms).
@@ -66,6 +61,11 @@ constexpr int brick_z_tile() {
   return P == 8 ? 4 : 1;
 }
 
+// Loads in the order the kernel needs them (see the kernel), chosen per
+// precision and degree by measurement on the 51M-DOF slab: FP64 p = 3 / 4 / 5
+// 1.454 -> 1.448, 1.268 -> 1.237, 1.145 -> 1.128 ms, FP32 p = 5 / 6 / 7 0.585 ->
+// 0.579, 0.549 -> 0.544, 0.558 -> 0.540 ms; slower at FP64 p = 2 (1.915 -> 1.930)
+// and p = 7 (1.090 -> 1.136 ms); no change at FP64 p = 6 and FP32 p = 2..4.
 template <typename T, int P>
 constexpr bool brick_ordered_loads() {
   return sizeof(T) == 8 ? (P >= 4 && P <= 6) : (P >= 6);
