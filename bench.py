@@ -577,7 +577,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library has "
-              f"no multi-GPU path, and this build runs on one GPU", file=sys.stderr)
+              f"no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
