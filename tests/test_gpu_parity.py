@@ -178,7 +178,9 @@ def test_assembled_matrix(p):
     assert rel_l2(to_np(csr.apply(to_dev(x))), A @ x) <= TOL64
 
 
-@pytest.mark.parametrize("p,quad,q", [(2, "gll", 0), (4, "gll", 0), (7, "gll", 0), (4, "gauss", 6)])
+@pytest.mark.parametrize("p,quad,q", [(2, "gll", 0), (4, "gll", 0), (5, "gll", 0), (6, "gll", 0),
+                                      (7, "gll", 0), (2, "gauss", 4), (4, "gauss", 6),
+                                      (7, "gauss", 9)])
 def test_apply_f32(p, quad, q):
     announce(f"apply f32 p{p} {quad}")
     spec = _spec(p, quad=quad, nq1d=q)
@@ -191,12 +193,14 @@ def test_apply_f32(p, quad, q):
     assert rel_l2(d, A.diagonal()) <= TOL32
 
 
-@pytest.mark.parametrize("quad,q", [("gll", 0), ("gauss", 5)])
-def test_apply_singular_sigma(quad, q):
+@pytest.mark.parametrize("p,quad,q,n", [(3, "gll", 0, (5, 3, 2)), (3, "gauss", 5, (5, 3, 2)),
+                                        (4, "gauss", 6, (4, 3, 2)), (7, "gauss", 9, (2, 2, 1))])
+def test_apply_singular_sigma(p, quad, q, n):
     """sigma_t = 0 makes sigma = sigma_l f f^T singular: det G = 0, so the mass
-    weight cannot be recovered from it and the kernels read the stored W|J|."""
-    announce(f"apply singular sigma {quad}")
-    spec = _spec(3, (5, 3, 2), quad=quad, nq1d=q).with_(sigma=(0.17, 0.0, 0.0))
+    weight cannot be recovered from it and the kernels read the stored W|J|
+    (for Gauss from p = 4 in FP64 through the flux loop's stored-weight copy)."""
+    announce(f"apply singular sigma p{p} {quad}")
+    spec = _spec(p, n, quad=quad, nq1d=q).with_(sigma=(0.17, 0.0, 0.0))
     prob, A, M, K = oracle_problem(spec)
     x = synth.uniform(106, spec.n_dof)
     kws = (dict(), dict(structured=False)) if quad == "gll" else (dict(),)
