@@ -33,15 +33,19 @@ def _warp(xyz, eps=0.04):
     return eps * np.stack([s, 0.7 * s, -0.5 * s], axis=1)
 
 
-def _problem(p, n, quad="gll", q=0):
-    spec = synth.BoxSpec(p=p, n=(n, n, n), quad=quad, nq1d=q, alpha=ALPHA,
-                         sigma=(1.0, 1.0, 1.0))
+def _problem(p, n, quad="gll", q=0, aniso=False):
+    """aniso: fibers along x with sigma_l = 2, sigma_t = 0.5, i.e. sigma =
+    diag(2, 0.5, 0.5); the normal flux sigma grad u . n still vanishes on the
+    faces and -div(sigma grad u) = pi^2 (2 + 0.5 + 0.5) u."""
+    sig = (2.0, 0.5, 0.5) if aniso else (1.0, 1.0, 1.0)
+    spec = synth.BoxSpec(p=p, n=(n, n, n), quad=quad, nq1d=q, alpha=ALPHA, sigma=sig,
+                         fiber=aniso)
     box = mf.Box.from_spec(spec)
     X = box.xyz.cpu().numpy()
     X = X + _warp(X)
     op = mf.Operator.from_spec(spec, box=box, xyz=to_dev(X))
     u_ex = np.cos(np.pi * X[:, 0]) * np.cos(np.pi * X[:, 1]) * np.cos(np.pi * X[:, 2])
-    b = op.apply_mass(to_dev((ALPHA + 3 * np.pi ** 2) * u_ex))
+    b = op.apply_mass(to_dev((ALPHA + np.pi ** 2 * sum(sig)) * u_ex))
     return spec, box, X, op, to_dev(u_ex), b
 
 
@@ -63,20 +67,21 @@ def _solve(spec, box, X, b, precision=torch.float64):
     return u, info
 
 
-def _error(p, n, quad="gll", q=0):
-    spec, box, X, op, u_ex, b = _problem(p, n, quad, q)
+def _error(p, n, quad="gll", q=0, aniso=False):
+    spec, box, X, op, u_ex, b = _problem(p, n, quad, q, aniso)
     u, _ = _solve(spec, box, X, b)
     return _mass_norm(op, u - u_ex)
 
 
-@pytest.mark.parametrize("p,quad,q", [(2, "gll", 0), (3, "gll", 0), (4, "gll", 0),
-                                      (3, "gauss", 5)])
-def test_h_convergence_rate(p, quad, q):
-    announce(f"h-convergence p={p} {quad}")
+@pytest.mark.parametrize("p,quad,q,aniso", [(2, "gll", 0, False), (3, "gll", 0, False),
+                                            (4, "gll", 0, False), (3, "gauss", 5, False),
+                                            (3, "gll", 0, True), (3, "gauss", 5, True)])
+def test_h_convergence_rate(p, quad, q, aniso):
+    announce(f"h-convergence p={p} {quad} aniso={aniso}")
     ns = (4, 8, 16)
-    errs = [_error(p, n, quad, q) for n in ns]
+    errs = [_error(p, n, quad, q, aniso) for n in ns]
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(ns) - 1)]
-    print(f"p = {p} {quad}: errors {errs}, rates {rates}", flush=True)
+    print(f"p = {p} {quad} aniso={aniso}: errors {errs}, rates {rates}", flush=True)
     # the finest pair is in the asymptotic range; the coarse pair may not be yet
     assert rates[-1] > p + 1 - 0.3, (errs, rates)
     assert rates[0] > p + 1 - 1.0, (errs, rates)
