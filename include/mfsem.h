@@ -30,6 +30,10 @@
  *     failing call on the same thread).  Arguments are validated on the host
  *     before any launch; a failed call leaves outputs untouched unless stated.
  *   - Vectors with a batch dimension are laid out [batch][n_dof], contiguous.
+ *     An operator may have no elements (A is then the zero matrix on its
+ *     nodes) and no DOFs; the vectors of an operator with n_dof == 0 have no
+ *     entries and may be NULL in mfsem_op_apply*, mfsem_op_diagonal and
+ *     mfsem_pcg*.
  *   - Local node numbering inside an element is i = a + P*(b + P*c), P = p+1,
  *     a along the first reference axis (fastest).
  */

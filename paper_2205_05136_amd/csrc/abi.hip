@@ -181,6 +181,14 @@ void check_op(const mfsem_op* op, int dtype) {
   else require(op->G32 != nullptr, "operator has no FP32 geometry (store_f32 = 0)");
 }
 
+// the vectors of an operator with DOFs must be given and distinct; with no
+// DOFs (an empty mesh) they have no entries and may be NULL
+void require_vectors(const mfsem_op& op, const void* x, const void* y) {
+  if (op.d.n_dof == 0) return;
+  require(x && y, "x or y is NULL");
+  require(x != y, "x and y must not alias");
+}
+
 void read_bad_flag(mfsem_op& op, hipStream_t s) {
   unsigned long long flags[3] = {0, 0, 0};
   MFSEM_HIP(hipMemcpyAsync(flags, op.bad, sizeof(flags), hipMemcpyDeviceToHost, s));
@@ -338,8 +346,7 @@ mfsem_status mfsem_op_apply(const mfsem_op* op, int32_t dtype, const void* x, vo
                             void* stream) {
   return guarded([&] {
     check_op(op, dtype);
-    require(x && y, "x or y is NULL");
-    require(x != y, "x and y must not alias");
+    require_vectors(*op, x, y);
     hipStream_t s = as_stream(stream);
     if (dtype == MFSEM_F64)
       launch_apply<double>(*op, static_cast<const double*>(x), static_cast<double*>(y), op->alpha, true, s);
@@ -352,8 +359,7 @@ mfsem_status mfsem_op_apply_add(const mfsem_op* op, int32_t dtype, const void* x
                                 void* stream) {
   return guarded([&] {
     check_op(op, dtype);
-    require(x && y, "x or y is NULL");
-    require(x != y, "x and y must not alias");
+    require_vectors(*op, x, y);
     hipStream_t s = as_stream(stream);
     if (dtype == MFSEM_F64)
       launch_apply<double>(*op, static_cast<const double*>(x), static_cast<double*>(y), op->alpha, true, s, true);
@@ -366,8 +372,7 @@ mfsem_status mfsem_op_apply_mass(const mfsem_op* op, int32_t dtype, const void* 
                                  void* stream) {
   return guarded([&] {
     check_op(op, dtype);
-    require(x && y, "x or y is NULL");
-    require(x != y, "x and y must not alias");
+    require_vectors(*op, x, y);
     hipStream_t s = as_stream(stream);
     if (dtype == MFSEM_F64)
       launch_apply<double>(*op, static_cast<const double*>(x), static_cast<double*>(y), 1.0, false, s);
@@ -379,7 +384,7 @@ mfsem_status mfsem_op_apply_mass(const mfsem_op* op, int32_t dtype, const void* 
 mfsem_status mfsem_op_diagonal(const mfsem_op* op, int32_t dtype, void* d, void* stream) {
   return guarded([&] {
     check_op(op, dtype);
-    require(d != nullptr, "d is NULL");
+    require(d != nullptr || op->d.n_dof == 0, "d is NULL");
     hipStream_t s = as_stream(stream);
     if (dtype == MFSEM_F64) launch_diag<double>(*op, static_cast<double*>(d), s);
     else launch_diag<float>(*op, static_cast<float*>(d), s);
@@ -601,8 +606,8 @@ mfsem_status pcg_entry(const mfsem_op* op, const mfsem_mg* mg, const double* b, 
   mfsem_status solve_status = MFSEM_OK;
   mfsem_status st = guarded([&] {
     check_op(op, MFSEM_F64);
-    require(b && x && opts && info && (ws || noalloc), "NULL argument");
-    require(b != x, "b and x must not alias");
+    require(opts && info && (ws || noalloc), "NULL argument");
+    require_vectors(*op, b, x);
     require(opts->max_it >= 1, "max_it must be >= 1");
     require(opts->rtol >= 0.0 && opts->atol >= 0.0 && (opts->rtol > 0.0 || opts->atol > 0.0),
             "need rtol > 0 or atol > 0");

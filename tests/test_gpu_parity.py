@@ -152,6 +152,36 @@ def test_apply_degenerate_meshes(p, n):
         assert float(z.abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("quad,q", [("gll", 0), ("gauss", 4)])
+@pytest.mark.parametrize("n_dof", [0, 7])
+def test_empty_mesh(quad, q, n_dof):
+    """No elements: A is the zero matrix on the (isolated) nodes, so every apply,
+    the mass and the diagonal are zero, y += A x leaves y as it was, CG with a
+    zero right-hand side stops at once, and with a nonzero one it reports the
+    breakdown p^T A p = 0."""
+    announce(f"empty mesh {quad} n_dof={n_dof}")
+    import types
+    dev = torch.device("cuda", torch.cuda.current_device())
+    dofs = types.SimpleNamespace(p=2, n=(0, 0, 0), n_elem=0, n_dof=n_dof, device=dev,
+                                 elem_dof=torch.empty((0, 27), dtype=torch.int32, device=dev),
+                                 xyz=torch.zeros((n_dof, 3), dtype=torch.float64, device=dev),
+                                 fiber=None)
+    op = mf.Operator(dofs, quad=quad, nq1d=q, structured=False, store_f32=True)
+    x = to_dev(synth.uniform(3, n_dof))
+    for v in (x, x.float()):
+        assert int(torch.count_nonzero(op.apply(v))) == 0
+        assert int(torch.count_nonzero(op.apply_mass(v))) == 0
+        y = torch.ones_like(v)
+        op.apply_add(v, y)
+        assert bool((y == 1).all())
+    assert int(torch.count_nonzero(op.diagonal())) == 0
+    u, info = mf.pcg(op, torch.zeros_like(x), rtol=1e-10)
+    assert info.status == [0] and info.iters == [0] and int(torch.count_nonzero(u)) == 0
+    if n_dof:
+        u, info = mf.pcg(op, x, rtol=1e-10, check=False)
+        assert info.status == [-6], info
+
+
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 6, 8])
 def test_assembled_matrix(p):
     """The matrix-based path: the CSR matrix assembled on the GPU equals the
