@@ -274,26 +274,34 @@ def test_full_size_properties(p):
     assert abs(vol - 420.0) <= 1e-9 * 420.0
 
 
-FULL_SIZE = {"slab-p7-51M": synth.C3_NI, "slab-p7-gauss-q9-51M": synth.C3_SEM,
-             "slab-p4-gauss-51M": synth.sweep(4, quad="gauss", nq1d=6)}
+FULL_SIZE = {"slab-p4-51M": synth.sweep(4), "slab-p7-51M": synth.C3_NI,
+             "slab-p7-gauss-q9-51M": synth.C3_SEM,
+             "slab-p4-gauss-51M": synth.sweep(4, quad="gauss", nq1d=6),
+             "box-p5-132M": synth.C5}
 
 
 @pytest.mark.parametrize("name", list(FULL_SIZE))
 def test_full_size_sampled_rows(name):
-    """At the 51M-DOF workload size, in the benchmark's launch configuration:
-    rows of A x against the oracle's element matrices, x_g = sin(0.37 g)."""
+    """At the workload sizes (51M and 132M DOFs), in the benchmark's launch
+    configuration: rows of A x against the oracle's element matrices,
+    x_g = sin(0.37 g); FP64 to 1e-12 and the FP32 kernel (FP32 G and vectors) to
+    1e-5 of the rows' scale."""
     announce(f"sampled rows {name}")
     spec = FULL_SIZE[name]
-    op = mf.Operator.from_spec(spec)
+    op = mf.Operator.from_spec(spec, store_f32=True)
     g = torch.arange(spec.n_dof, device="cuda", dtype=torch.float64)
     x = torch.sin(0.37 * g)
+    del g
     y = op.apply(x)
+    y32 = op.apply(x.float())
     rng = np.random.default_rng(1)
     rows = np.concatenate([rng.integers(0, spec.n_dof, 24), [0, spec.n_dof - 1]])
     ref = oop.apply_rows(spec, lambda gg: np.sin(0.37 * np.asarray(gg, dtype=np.float64)), rows)
-    got = to_np(y[torch.as_tensor(rows, device="cuda")])
+    idx = torch.as_tensor(rows, device="cuda")
+    got, got32 = to_np(y[idx]), to_np(y32[idx])
     scale = np.abs(ref).max()
     assert np.max(np.abs(got - ref)) <= 1e-12 * scale, (got - ref)
+    assert np.max(np.abs(got32 - ref)) <= 1e-5 * scale, (got32 - ref)
 
 
 @pytest.mark.parametrize("spec", [synth.C3_NI, synth.C3_SEM], ids=["gll-q8", "gauss-q9"])
