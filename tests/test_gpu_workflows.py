@@ -304,6 +304,32 @@ def test_full_size_sampled_rows(name):
     assert np.max(np.abs(got32 - ref)) <= 1e-5 * scale, (got32 - ref)
 
 
+def test_c4_full_size_batch_sampled_rows():
+    """c4 at full size as the benchmark launches it: one apply over the batch of 8
+    per-element conductivity sets (8 x 2,146,689 DOFs); sampled rows of every
+    member against the oracle's element matrices with that member's sigma, FP64
+    to 1e-12 and FP32 to 1e-5 of the rows' scale."""
+    announce("c4 full-size batch sampled rows")
+    spec = synth.C4
+    B = 8
+    sig = synth.element_sigma(4, B, spec.n_elem)
+    op = mf.Operator.from_spec(spec, sigma=to_dev(sig), store_f32=True)
+    g = torch.arange(spec.n_dof, device="cuda", dtype=torch.float64)
+    x = torch.stack([torch.sin(0.37 * g + 0.1 * b) for b in range(B)]).contiguous()
+    y, y32 = op.apply(x), op.apply(x.float())
+    rng = np.random.default_rng(2)
+    for b in range(B):
+        rows = np.concatenate([rng.integers(0, spec.n_dof, 6), [0, spec.n_dof - 1]])
+        ref = oop.apply_rows(
+            spec, lambda gg: np.sin(0.37 * np.asarray(gg, dtype=np.float64) + 0.1 * b), rows,
+            sigma=sig[b])
+        idx = torch.as_tensor(rows, device="cuda")
+        got, got32 = to_np(y[b][idx]), to_np(y32[b][idx])
+        scale = np.abs(ref).max()
+        assert np.max(np.abs(got - ref)) <= 1e-12 * scale, (b, got - ref)
+        assert np.max(np.abs(got32 - ref)) <= 1e-5 * scale, (b, got32 - ref)
+
+
 @pytest.mark.parametrize("spec", [synth.C3_NI, synth.C3_SEM], ids=["gll-q8", "gauss-q9"])
 def test_c3_full_size_solve_certificate(spec):
     """c3 at full size (51,086,841 DOFs, p = 7, chain 7 -> 5 -> 3 -> 1): the
