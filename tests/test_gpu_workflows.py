@@ -330,6 +330,33 @@ def test_c4_full_size_batch_sampled_rows():
         assert np.max(np.abs(got32 - ref)) <= 1e-5 * scale, (b, got32 - ref)
 
 
+def test_c4_full_size_batch_grad_sampled_elements():
+    """The dL/dsigma contraction g[e, c] = w^T (dA/dsigma_{e,c}) u at the c4 size for
+    the batch of 8, as the benchmark's backward pass runs it; sampled elements of
+    every member against the oracle's explicit dK_e (which do not depend on sigma,
+    A being linear in it), to 1e-12 of the sampled entries' scale."""
+    announce("c4 full-size batch gradient, sampled elements")
+    spec = synth.C4
+    B = 8
+    sig = synth.element_sigma(4, B, spec.n_elem)
+    op = mf.Operator.from_spec(spec, sigma=to_dev(sig))
+    g = torch.arange(spec.n_dof, device="cuda", dtype=torch.float64)
+    u = torch.stack([torch.sin(0.37 * g + 0.1 * b) for b in range(B)]).contiguous()
+    w = torch.stack([torch.cos(0.23 * g + 0.2 * b) for b in range(B)]).contiguous()
+    grad = to_np(op.grad_sigma(u, w)).reshape(B, spec.n_elem, 3)
+    prob = oop.Problem(spec)
+    rng = np.random.default_rng(3)
+    els = np.concatenate([rng.integers(0, spec.n_elem, 14), [0, spec.n_elem - 1]])
+    _, _, dK = prob.elem_matrices(els, parts=True)
+    ed = prob.elem_dof[els]
+    for b in range(B):
+        ub = np.sin(0.37 * ed.astype(np.float64) + 0.1 * b)
+        wb = np.cos(0.23 * ed.astype(np.float64) + 0.2 * b)
+        ref = np.einsum("ceij,ei,ej->ec", dK, wb, ub)
+        got = grad[b][els]
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.abs(ref).max(), (b, got - ref)
+
+
 @pytest.mark.parametrize("spec", [synth.C3_NI, synth.C3_SEM], ids=["gll-q8", "gauss-q9"])
 def test_c3_full_size_solve_certificate(spec):
     """c3 at full size (51,086,841 DOFs, p = 7, chain 7 -> 5 -> 3 -> 1): the
