@@ -285,7 +285,7 @@ def test_full_size_sampled_rows(name):
     """At the workload sizes (51M and 132M DOFs), in the benchmark's launch
     configuration: rows of A x against the oracle's element matrices,
     x_g = sin(0.37 g); FP64 to 1e-12 and the FP32 kernel (FP32 G and vectors) to
-    1e-5 of the rows' scale."""
+    1e-5 of the rows' scale; and diagonal entries of the same rows."""
     announce(f"sampled rows {name}")
     spec = FULL_SIZE[name]
     op = mf.Operator.from_spec(spec, store_f32=True)
@@ -302,6 +302,12 @@ def test_full_size_sampled_rows(name):
     scale = np.abs(ref).max()
     assert np.max(np.abs(got - ref)) <= 1e-12 * scale, (got - ref)
     assert np.max(np.abs(got32 - ref)) <= 1e-5 * scale, (got32 - ref)
+    # diagonal entries A_gg of some of the rows (the row times the indicator of g)
+    d, d32 = op.diagonal(), op.diagonal(torch.float32)
+    for gg in rows[:6]:
+        a_gg = oop.apply_rows(spec, lambda h: (np.asarray(h) == gg).astype(np.float64), [gg])[0]
+        assert abs(float(d[int(gg)]) - a_gg) <= 1e-12 * abs(a_gg), (gg, float(d[int(gg)]), a_gg)
+        assert abs(float(d32[int(gg)]) - a_gg) <= 1e-5 * abs(a_gg), (gg, float(d32[int(gg)]), a_gg)
 
 
 def test_c4_full_size_batch_sampled_rows():
