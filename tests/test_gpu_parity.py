@@ -263,6 +263,27 @@ def test_apply_batch_sigma():
     assert rel_l2(y2[0], A0 @ x[0]) <= TOL64
 
 
+@pytest.mark.parametrize("p,q", [(3, 5), (5, 7)])
+def test_apply_batch_sigma_gauss(p, q):
+    """The SEM (Gauss) kernels over a batch of 3 per-element sigma sets, FP64 and
+    FP32, the diagonal and the mass of every member against the oracle."""
+    announce(f"apply gauss batch of 3 sigma sets p={p} q={q}")
+    spec = _spec(p, (4, 3, 2), quad="gauss", nq1d=q)
+    sig = synth.element_sigma(37 + p, 3, spec.n_elem)
+    op = mf.Operator.from_spec(spec, sigma=to_dev(sig), store_f32=True)
+    x = synth.uniform(104 + p, (3, spec.n_dof))
+    y = to_np(op.apply(to_dev(x)))
+    y32 = to_np(op.apply(to_dev(x, torch.float32)))
+    d = to_np(op.diagonal())
+    m = to_np(op.apply_mass(to_dev(x)))
+    for b in range(3):
+        A, M, _ = oop.Problem(spec, sigma=sig[b]).assemble()
+        assert rel_l2(y[b], A @ x[b]) <= TOL64, b
+        assert rel_l2(y32[b], A @ x[b]) <= TOL32, b
+        assert rel_l2(d[b], A.diagonal()) <= TOL64, b
+        assert rel_l2(m[b], M @ x[b]) <= TOL64, b
+
+
 @pytest.mark.parametrize("p,n", [(5, (9, 2, 2)), (6, (8, 1, 2)), (7, (3, 1, 3))])
 def test_apply_batch_ragged_bricks_f64_f32(p, n):
     """Batched applies (two sigma sets) on meshes whose last lattice brick is
