@@ -363,19 +363,29 @@ def test_c4_full_size_batch_grad_sampled_elements():
         assert np.max(np.abs(got - ref)) <= 1e-12 * np.abs(ref).max(), (b, got - ref)
 
 
-@pytest.mark.parametrize("spec", [synth.C3_NI, synth.C3_SEM], ids=["gll-q8", "gauss-q9"])
-def test_c3_full_size_solve_certificate(spec):
-    """c3 at full size (51,086,841 DOFs, p = 7, chain 7 -> 5 -> 3 -> 1): the
-    FP64 and the mixed-precision solves to 1e-10, certified against the oracle
-    where it cannot solve.  On sampled rows, b - A x with the oracle's element
-    matrices (i) stays within 10x the per-row RMS the tolerance allows,
+# the benchmark's solves at full size: its default workload (p = 4), the p-sweep's
+# ends and c3 (GLL and Gauss), each with the benchmark's degree chain
+FULL_SOLVES = {"slab-p4-51M": (synth.sweep(4), (("p", 2), ("p", 1))),
+               "slab-p2-51M": (synth.sweep(2), (("p", 1),)),
+               "slab-p4-gauss-51M": (synth.sweep(4, quad="gauss", nq1d=6), (("p", 2), ("p", 1))),
+               "c3-gll-q8": (synth.C3_NI, (("p", 5), ("p", 3), ("p", 1))),
+               "c3-gauss-q9": (synth.C3_SEM, (("p", 5), ("p", 3), ("p", 1)))}
+
+
+@pytest.mark.parametrize("name", list(FULL_SOLVES))
+def test_full_size_solve_certificate(name):
+    """The benchmark's solves at full size (about 51M DOFs): the FP64 and the
+    mixed-precision solves to 1e-10, certified against the oracle where it
+    cannot solve.  On sampled rows, b - A x with the oracle's element matrices
+    (i) stays within 10x the per-row RMS the tolerance allows,
     1e-10 ||b|| / sqrt(N), and (ii) equals the GPU's own true residual, which
     is within the tolerance over the whole vector, to 1e-11 max|b|: x is about
     1e3 times larger than b here (the mass term dominates and the elements are
-    small), so each row cancels stiffness terms of order 1e2 |b| summed over
-    4096 products, and FP64 rounding of those terms is ~1e-12 |b|.  The two
+    small), so each row cancels stiffness terms of order 1e2 |b| summed over up
+    to 4096 products, and FP64 rounding of those terms is ~1e-12 |b|.  The two
     solutions agree to 1e-8."""
-    announce(f"c3 full-size solve certificate {spec.quad}")
+    announce(f"full-size solve certificate {name}")
+    spec, chain = FULL_SOLVES[name]
     f = torch.as_tensor(synth.uniform(3, spec.n_dof), device="cuda")
     rng = np.random.default_rng(3)
     rows = np.concatenate([rng.integers(0, spec.n_dof, 16), [0, spec.n_dof - 1]])
@@ -383,8 +393,7 @@ def test_c3_full_size_solve_certificate(spec):
     fmax, fnorm = float(f.abs().max()), float(torch.linalg.norm(f))
     sols = {}
     for precision in (torch.float64, torch.float32):
-        ops, mg = mf.hierarchy(spec, coarsening=(("p", 5), ("p", 3), ("p", 1)), degree=3,
-                               precision=precision)
+        ops, mg = mf.hierarchy(spec, coarsening=chain, degree=3, precision=precision)
         x, info = mf.pcg(ops[0], f, mg=mg, rtol=1e-10, max_it=100)
         assert info.status == [0], info
         r = f - ops[0].apply(x)
