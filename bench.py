@@ -71,20 +71,26 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def sem_reads_index(p, w):
+    """Whether the Gauss (SEM) kernel reads the element-to-node index on these
+    structured meshes: its lattice form (node numbers computed) runs in FP64 up
+    to p = 6 and in FP32 up to p = 4 (the library's choice, by measurement)."""
+    return p > (6 if w == 8 else 4)
+
+
 def apply_kernel(spec):
     """The kernel that performs y += A x for this workload, its source file, and
     the model of the bytes one launch must move: one read of x, one read and one
     write of y, the 6 stored G entries per quadrature point and 1/det(sigma) per
     element (the mass weight W|J| is recovered from det G, so no W|J| is read),
-    plus the element-to-node index for the Gauss kernel (the lattice kernel
-    computes node numbers)."""
+    plus the element-to-node index where the Gauss kernel reads it (the lattice
+    kernels compute node numbers)."""
     P = spec.p + 1
+    base = "8*(x + y read + y write)*N + 48*n_elem*q^3 (G) + 8*n_elem (1/det sigma)"
     if spec.quad == "gll":
-        return (f"ax_brick_kernel<double,{P}>", "ax_brick.hip",
-                "8*(x + y read + y write)*N + 48*n_elem*q^3 (G) + 8*n_elem (1/det sigma)")
+        return (f"ax_brick_kernel<double,{P}>", "ax_brick.hip", base)
     return (f"ax_sem_kernel<double,{P},{spec.q}>", "ax.hip",
-            "8*(x + y read + y write)*N + 48*n_elem*q^3 (G) + 8*n_elem (1/det sigma) "
-            "+ 4*n_elem*(p+1)^3 (index)")
+            base + (" + 4*n_elem*(p+1)^3 (index)" if sem_reads_index(spec.p, 8) else ""))
 
 
 def algorithmic_bytes(spec, n_elem, n_dof, w, quad):
@@ -92,9 +98,10 @@ def algorithmic_bytes(spec, n_elem, n_dof, w, quad):
     q3 = spec.q ** 3
     P3 = (spec.p + 1) ** 3
     g = 6 * n_elem * q3 * w
-    if quad == "gll":
-        return 3 * w * n_dof + g + w * n_elem
-    return 3 * w * n_dof + g + w * n_elem + 4 * n_elem * P3
+    b = 3 * w * n_dof + g + w * n_elem
+    if quad != "gll" and sem_reads_index(spec.p, w):
+        b += 4 * n_elem * P3
+    return b
 
 
 def algorithmic_flops(spec, n_elem, n_dof, quad):

@@ -185,12 +185,25 @@ struct SemCfg {
 template <typename T, int P, int Q>
 constexpr int sem_min_waves() { return (sizeof(T) == 8 && P >= 6 && Q <= 9) ? 3 : 1; }
 
-template <typename T, int P, int Q, bool STIFF>
+// Structured lattices: the workgroup's NE elements are a brick along x, whose
+// node lattice ((NE p + 1) x P x P nodes) is gathered once with coalesced rows
+// (node numbers computed, no element-to-node index) and summed once, through
+// LDS atomics, before one global atomic per lattice node (as the SEM-NI lattice
+// kernel does).  Chosen per precision and degree by measurement on the 51M-DOF
+// slab (q = p + 2): FP64 p = 2..6 4.64 / 2.99 / 2.18 / 1.83 / 1.72 -> 4.26 / 2.75 /
+// 2.04 / 1.77 / 1.66 ms but p = 7 1.67 -> 1.69 ms; FP32 p = 2..4 3.60 / 1.78 /
+// 1.44 -> 2.25 / 1.61 / 1.29 ms but p = 5..7 slower (up to 1.11 against 0.96 ms
+// at p = 7): the LDS atomics of the lattice add to the LDS traffic that bounds the
+// high-degree kernels.
+template <typename T, int P, int Q>
+constexpr bool sem_lattice() { return sizeof(T) == 8 ? P <= 7 : P <= 5; }
+
+template <typename T, int P, int Q, bool STIFF, bool LAT = false>
 __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())) void ax_sem_kernel(
     int64_t n_elem, int64_t n_dof, const int32_t* __restrict__ ed, const T* __restrict__ G,
     const T* __restrict__ WJ, const T* __restrict__ idet, T alpha, const T* __restrict__ Btab,
     const T* __restrict__ Dqtab, const T* __restrict__ wtab, const T* __restrict__ x,
-    T* __restrict__ y) {
+    T* __restrict__ y, int lnx, int lny) {
   using C = SemCfg<P, Q>;
   constexpr int P2 = C::P2, P3 = C::P3, Q2 = C::Q2, Q3 = C::Q3, NE = C::NE;
   // lane-uniform entries (z direction) are compile-time constants
@@ -204,8 +217,29 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
   const int tid = threadIdx.x;
   const int le = tid / Q2, pq = tid % Q2;
   const int i = pq % Q, j = pq / Q;
-  const int64_t e = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NE + le;
-  const bool active = (le < NE) && (e < n_elem);
+  // LAT: a brick of NE elements along x of a structured lattice (see
+  // sem_lattice), its node lattice of LX x P x P nodes gathered once and summed once
+  constexpr int p = P - 1, LX = NE * p + 1, LN = LX * P2;
+  int64_t e;
+  bool active;
+  int nex = 0;
+  int64_t I0 = 0, J0 = 0, K0 = 0, NX = 0, NY = 0;
+  if constexpr (LAT) {
+    const int nbx = (lnx + NE - 1) / NE;
+    const int brick = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int bxi = brick % nbx, byi = (brick / nbx) % lny, bzi = brick / (nbx * lny);
+    nex = min(NE, lnx - bxi * NE);
+    e = (int64_t)(bxi * NE + le) + (int64_t)lnx * (byi + (int64_t)lny * bzi);
+    active = le < nex;
+    NX = (int64_t)p * lnx + 1;
+    NY = (int64_t)p * lny + 1;
+    I0 = (int64_t)bxi * NE * p;
+    J0 = (int64_t)byi * p;
+    K0 = (int64_t)bzi * p;
+  } else {
+    e = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NE + le;
+    active = (le < NE) && (e < n_elem);
+  }
   const bool node = active && i < P && j < P;  // lane owns node pencil (a=i, b=j)
   const bool rowb = active && j < P;           // lane owns (k1=i, b=j)
   const int bt = blockIdx.y;
@@ -218,18 +252,28 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
   T* b2 = s2 + le * C::L2;
   T* b3 = s3 + le * C::L3;
 
-  if (node) {
+  if constexpr (LAT) {
+    // the brick's node lattice into s3 (free until the z-interpolation)
+    for (int n = tid; n < LN; n += blockDim.x) {
+      const int ii = n % LX, jj = (n / LX) % P, kk = n / (LX * P);
+      const bool in = ii <= nex * p;
+      const T v = x[in ? (I0 + ii) + NX * ((J0 + jj) + NY * (K0 + kk)) : 0];
+      s3[n] = in ? v : T(0);
+    }
+  } else if (node) {
 #pragma unroll
     for (int c = 0; c < P; ++c) b1[c * P2 + j * P + i] = x[ed[e * P3 + c * P2 + j * P + i]];
   }
   __syncthreads();
   // x-interpolation: b2[c][b][k1] = sum_a B[k1][a] u[c][b][a]
   if (rowb) {
+    const T* u = LAT ? s3 + le * p + LX * j : b1 + j * P;
+    constexpr int CS = LAT ? LX * P : P2;
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       T s = 0;
 #pragma unroll
-      for (int a = 0; a < P; ++a) s += sB[i * P + a] * b1[c * P2 + j * P + a];
+      for (int a = 0; a < P; ++a) s += sB[i * P + a] * u[c * CS + a];
       b2[c * P * Q + j * Q + i] = s;
     }
   }
@@ -350,6 +394,10 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
   }
   __syncthreads();
   // y-pass: b2[c][b][k1] = sum_k2 B[k2][b] b1[c][k2][k1]
+  if constexpr (LAT) {
+    // the lattice the x-pass sums into (s3 is free after the transposed passes)
+    for (int n = tid; n < LN; n += blockDim.x) s3[n] = T(0);
+  }
   if (rowb) {
 #pragma unroll
     for (int c = 0; c < P; ++c) {
@@ -367,7 +415,19 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
       T s = 0;
 #pragma unroll
       for (int k = 0; k < Q; ++k) s += sB[k * P + i] * b2[c * P * Q + j * Q + k];
-      atomic_add(&y[ed[e * P3 + c * P2 + j * P + i]], s);
+      if constexpr (LAT)
+        __hip_atomic_fetch_add(&s3[le * p + i + LX * (j + P * c)], s, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+      else
+        atomic_add(&y[ed[e * P3 + c * P2 + j * P + i]], s);
+    }
+  }
+  if constexpr (LAT) {
+    __syncthreads();
+    for (int n = tid; n < LN; n += blockDim.x) {
+      const int ii = n % LX, jj = (n / LX) % P, kk = n / (LX * P);
+      if (ii > nex * p) continue;
+      atomic_add(y + (I0 + ii) + NX * ((J0 + jj) + NY * (K0 + kk)), s3[n]);
     }
   }
 }
@@ -431,10 +491,22 @@ void run_sem(const mfsem_op& op, const T* x, T* y, T alpha, hipStream_t s) {
   using C = SemCfg<P, Q>;
   const unsigned nb = blocks_for(op.d.n_elem, C::NE);
   const T* tab = tables_of<T>(op);
+  if constexpr (STIFF && sem_lattice<T, P, Q>()) {
+    if (op.structured) {
+      const unsigned nbl = (unsigned)(((op.lat[0] + C::NE - 1) / C::NE) * (int64_t)op.lat[1] *
+                                      op.lat[2]);
+      ax_sem_kernel<T, P, Q, STIFF, true><<<dim3(nbl, op.d.batch), dim3(C::THREADS), 0, s>>>(
+          op.d.n_elem, op.d.n_dof, op.d.elem_dof, G_of<T>(op), WJ_of<T>(op),
+          op.use_det ? idet_of<T>(op) : nullptr, alpha, tab + op.off.B, tab + op.off.Dq,
+          tab + op.off.w, x, y, op.lat[0], op.lat[1]);
+      MFSEM_LAUNCH("ax_sem_kernel (lattice)");
+      return;
+    }
+  }
   ax_sem_kernel<T, P, Q, STIFF><<<dim3(nb, op.d.batch), dim3(C::THREADS), 0, s>>>(
       op.d.n_elem, op.d.n_dof, op.d.elem_dof, G_of<T>(op), WJ_of<T>(op),
       op.use_det ? idet_of<T>(op) : nullptr, alpha, tab + op.off.B, tab + op.off.Dq,
-      tab + op.off.w, x, y);
+      tab + op.off.w, x, y, 0, 0);
   MFSEM_LAUNCH("ax_sem_kernel");
 }
 
