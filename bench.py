@@ -74,8 +74,8 @@ def log(*a):
 def sem_reads_index(p, w):
     """Whether the Gauss (SEM) kernel reads the element-to-node index on these
     structured meshes: its lattice form (node numbers computed) runs in FP64 up
-    to p = 6 and in FP32 up to p = 4 (the library's choice, by measurement)."""
-    return p > (6 if w == 8 else 4)
+    to p = 6 and in FP32 at every degree (the library's choice, by measurement)."""
+    return w == 8 and p > 6
 
 
 def apply_kernel(spec):

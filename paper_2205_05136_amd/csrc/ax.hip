@@ -187,16 +187,18 @@ constexpr int sem_min_waves() { return (sizeof(T) == 8 && P >= 6 && Q <= 9) ? 3 
 
 // Structured lattices: the workgroup's NE elements are a brick along x, whose
 // node lattice ((NE p + 1) x P x P nodes) is gathered once with coalesced rows
-// (node numbers computed, no element-to-node index) and summed once, through
-// LDS atomics, before one global atomic per lattice node (as the SEM-NI lattice
-// kernel does).  Chosen per precision and degree by measurement on the 51M-DOF
-// slab (q = p + 2): FP64 p = 2..6 4.64 / 2.99 / 2.18 / 1.83 / 1.72 -> 4.26 / 2.75 /
-// 2.04 / 1.77 / 1.66 ms but p = 7 1.67 -> 1.69 ms; FP32 p = 2..4 3.60 / 1.78 /
-// 1.44 -> 2.25 / 1.61 / 1.29 ms but p = 5..7 slower (up to 1.11 against 0.96 ms
-// at p = 7): the LDS atomics of the lattice add to the LDS traffic that bounds the
-// high-degree kernels.
+// (node numbers computed, no element-to-node index); each element's results go
+// to its own node buffer and every lattice node sums its one or two
+// contributions (two on an element boundary along x) before one global atomic
+// per lattice node (the element form adds every element node with its own
+// atomic).  Chosen per precision and degree by measurement on the 51M-DOF slab
+// (q = p + 2): FP64 p = 2..6 4.64 / 2.98 / 2.19 / 1.85 / 1.73 -> 4.27 / 2.80 /
+// 2.07 / 1.79 / 1.68 ms, but p = 7 1.72 -> 1.76 ms; FP32 p = 2..7 3.60 / 1.78 /
+// 1.46 / 1.17 / 1.01 / 0.98 -> 2.11 / 1.42 / 1.11 / 0.96 / 0.91 / 0.96 ms.  Summing
+// the lattice with LDS atomics instead measured the same in FP64 and up to 16%
+// slower than the element form in FP32 (p = 7), whose LDS is the busier.
 template <typename T, int P, int Q>
-constexpr bool sem_lattice() { return sizeof(T) == 8 ? P <= 7 : P <= 5; }
+constexpr bool sem_lattice() { return sizeof(T) == 8 ? P <= 7 : true; }
 
 template <typename T, int P, int Q, bool STIFF, bool LAT = false>
 __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())) void ax_sem_kernel(
@@ -218,7 +220,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
   const int le = tid / Q2, pq = tid % Q2;
   const int i = pq % Q, j = pq / Q;
   // LAT: a brick of NE elements along x of a structured lattice (see
-  // sem_lattice), its node lattice of LX x P x P nodes gathered once and summed once
+  // sem_lattice), its node lattice of LX x P x P nodes gathered and written once
   constexpr int p = P - 1, LX = NE * p + 1, LN = LX * P2;
   int64_t e;
   bool active;
@@ -394,10 +396,6 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
   }
   __syncthreads();
   // y-pass: b2[c][b][k1] = sum_k2 B[k2][b] b1[c][k2][k1]
-  if constexpr (LAT) {
-    // the lattice the x-pass sums into (s3 is free after the transposed passes)
-    for (int n = tid; n < LN; n += blockDim.x) s3[n] = T(0);
-  }
   if (rowb) {
 #pragma unroll
     for (int c = 0; c < P; ++c) {
@@ -416,8 +414,7 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
 #pragma unroll
       for (int k = 0; k < Q; ++k) s += sB[k * P + i] * b2[c * P * Q + j * Q + k];
       if constexpr (LAT)
-        __hip_atomic_fetch_add(&s3[le * p + i + LX * (j + P * c)], s, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        b1[c * P2 + j * P + i] = s;  // the element's node buffer (free after the y-pass)
       else
         atomic_add(&y[ed[e * P3 + c * P2 + j * P + i]], s);
     }
@@ -427,7 +424,12 @@ __global__ __launch_bounds__((SemCfg<P, Q>::THREADS), (sem_min_waves<T, P, Q>())
     for (int n = tid; n < LN; n += blockDim.x) {
       const int ii = n % LX, jj = (n / LX) % P, kk = n / (LX * P);
       if (ii > nex * p) continue;
-      atomic_add(y + (I0 + ii) + NX * ((J0 + jj) + NY * (K0 + kk)), s3[n]);
+      // the node's contributions: its element, and the previous one on an
+      // element boundary along x
+      const int el = min(ii / p, nex - 1), a = ii - el * p;
+      T sum = s1[el * C::L1 + kk * P2 + jj * P + a];
+      if (a == 0 && el > 0) sum += s1[(el - 1) * C::L1 + kk * P2 + jj * P + p];
+      atomic_add(y + (I0 + ii) + NX * ((J0 + jj) + NY * (K0 + kk)), sum);
     }
   }
 }
