@@ -152,6 +152,25 @@ def test_apply_degenerate_meshes(p, n):
         assert float(z.abs().max()) == 0.0
 
 
+# The same shapes for the Gauss kernel, whose lattice form (structured meshes)
+# takes bricks of several elements along x: one element, one ragged brick, a
+# column of single-element bricks.
+GAUSS_EDGE_CASES = [(p, n) for p in (1, 2, 4, 6, 7) for n in ((1, 1, 1), (9, 1, 1), (1, 5, 3))]
+
+
+@pytest.mark.parametrize("p,n", GAUSS_EDGE_CASES,
+                         ids=[f"p{c[0]}-{c[1][0]}x{c[1][1]}x{c[1][2]}" for c in GAUSS_EDGE_CASES])
+def test_apply_degenerate_meshes_gauss(p, n):
+    announce(f"apply degenerate gauss p{p} {n}")
+    spec = synth.slab(p, n, quad="gauss", nq1d=p + 2)
+    prob, A, M, K = oracle_problem(spec)
+    x = synth.uniform(107, spec.n_dof)
+    for kw in (dict(), dict(structured=False)):
+        op, _ = _op(spec, store_f32=True, **kw)
+        assert rel_l2(to_np(op.apply(to_dev(x))), A @ x) <= TOL64, kw
+        assert rel_l2(to_np(op.apply(to_dev(x, torch.float32))), A @ x) <= TOL32, kw
+
+
 @pytest.mark.parametrize("quad,q", [("gll", 0), ("gauss", 4)])
 @pytest.mark.parametrize("n_dof", [0, 7])
 def test_empty_mesh(quad, q, n_dof):
