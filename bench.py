@@ -428,22 +428,30 @@ def cpu_pcg_baseline(spec, chain, degree, max_dofs=1_000_000):
 def matrix_based(mf, op, x, t_mf_ms, spec, max_bytes=40e9):
     """The paper's matrix-based comparison on the GPU: assemble A in CSR
     (mfsem_csr_assemble) and time its product (mfsem_csr_spmv) beside the
-    matrix-free kernel, outside the timed steps.  Skipped when the matrix would
-    exceed max_bytes."""
+    matrix-free kernel, outside the timed steps.  The top-level fields are the
+    element pattern (every pair of nodes sharing an element, as a standard
+    assembly stores it); `coupled` holds the same for the pattern without
+    collocation's zeros.  Skipped when a matrix would exceed max_bytes."""
+    if spec.quad != "gll":
+        return {"skipped": "the assembled-matrix path covers GLL (SEM-NI) operators"}
+    out = _csr_point(mf, op, x, t_mf_ms, spec, "element", max_bytes)
+    out["coupled"] = _csr_point(mf, op, x, t_mf_ms, spec, "coupled", max_bytes)
+    return out
+
+
+def _csr_point(mf, op, x, t_mf_ms, spec, pattern, max_bytes):
     import ctypes
     import torch
     from paper_2205_05136_amd import _lib as L
-    if spec.quad != "gll":
-        return {"skipped": "the assembled-matrix path covers GLL (SEM-NI) operators"}
     nnz = ctypes.c_int64()
-    L.check(L.load().mfsem_csr_nnz(op.handle, ctypes.byref(nnz)))
+    L.check(L.load().mfsem_csr_nnz(op.handle, mf.CsrMatrix.PATTERNS[pattern], ctypes.byref(nnz)))
     nbytes = 12 * nnz.value + 8 * (spec.n_dof + 1)
     if nbytes > max_bytes:
         return {"skipped": f"{nbytes / 1e9:.1f} GB matrix"}
     E = lambda: torch.cuda.Event(enable_timing=True)
     a, b = E(), E()
     a.record()
-    A = mf.CsrMatrix(op)
+    A = mf.CsrMatrix(op, pattern)
     b.record()
     torch.cuda.synchronize()
     t_asm = a.elapsed_time(b)

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define MFSEM_ABI_VERSION 8
+#define MFSEM_ABI_VERSION 9
 #define MFSEM_MAX_P 8
 
 typedef enum {
@@ -253,17 +253,26 @@ mfsem_status mfsem_op_grad_sigma(const mfsem_op* op, const double* u, const doub
  * comparison: the global matrix from the element matrices, Alg. 2, and sparse
  * matrix-vector products, Section 4), for operators on a structured lattice
  * with GLL quadrature, batch 1 and FP64 geometry (EUNSUPPORTED otherwise).
- * CSR with the element-connectivity pattern: row g holds, in increasing
- * column order, every node of every element containing node g (up to
- * (2p+1)^3), explicit zeros included; alpha is the operator's at assembly.  */
+ * CSR, row g in increasing column order, in one of two patterns:
+ *   MFSEM_CSR_ELEMENT  every node of every element containing node g (up to
+ *                      (2p+1)^3 per row), the explicit zeros of collocation
+ *                      included, as a standard assembly of full element
+ *                      matrices stores them;
+ *   MFSEM_CSR_COUPLED  only the nodes of that set sharing at least one
+ *                      lattice coordinate with node g: the pairs GLL
+ *                      collocation can make non-zero (about 0.43 of the
+ *                      element pattern's entries at p = 4).
+ * Both give the same products; alpha is the operator's at assembly.  An
+ * unknown pattern is EINVAL.                                                 */
+typedef enum { MFSEM_CSR_ELEMENT = 0, MFSEM_CSR_COUPLED = 1 } mfsem_csr_pattern;
 
-/* Number of stored entries. [host] */
-mfsem_status mfsem_csr_nnz(const mfsem_op* op, int64_t* nnz);
+/* Number of stored entries in the pattern. [host] */
+mfsem_status mfsem_csr_nnz(const mfsem_op* op, int pattern, int64_t* nnz);
 
 /* Fill row_ptr [n_dof+1] (int64), col [nnz] (int32) and val [nnz] (FP64),
- * all [device] and caller-sized from mfsem_csr_nnz.                         */
-mfsem_status mfsem_csr_assemble(const mfsem_op* op, int64_t* row_ptr, int32_t* col, double* val,
-                                void* stream);
+ * all [device] and caller-sized from mfsem_csr_nnz with the same pattern.   */
+mfsem_status mfsem_csr_assemble(const mfsem_op* op, int pattern, int64_t* row_ptr, int32_t* col,
+                                double* val, void* stream);
 
 /* y = A x with a CSR matrix; x, y [device][n_rows] FP64, not aliased.  nnz
  * [host] is the number of stored entries (row_ptr[n_rows], from

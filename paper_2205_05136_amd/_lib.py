@@ -93,8 +93,8 @@ PROTOTYPES = {
     "mfsem_op_apply_mass": (_ST, [_P, C.c_int32, _P, _P, _P]),
     "mfsem_op_diagonal": (_ST, [_P, C.c_int32, _P, _P]),
     "mfsem_op_grad_sigma": (_ST, [_P, _P, _P, C.c_double, _P, _P]),
-    "mfsem_csr_nnz": (_ST, [_P, C.POINTER(C.c_int64)]),
-    "mfsem_csr_assemble": (_ST, [_P, _P, _P, _P, _P]),
+    "mfsem_csr_nnz": (_ST, [_P, C.c_int, C.POINTER(C.c_int64)]),
+    "mfsem_csr_assemble": (_ST, [_P, C.c_int, _P, _P, _P, _P]),
     "mfsem_csr_spmv": (_ST, [C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P]),
     "mfsem_extrapolate": (_ST, [C.c_int64, _P, _P, _P, _P]),
     "mfsem_mg_workspace_bytes": (_ST, [C.POINTER(MgDesc), C.POINTER(C.c_size_t)]),

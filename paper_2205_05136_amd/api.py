@@ -224,17 +224,26 @@ class Operator:
 # ----------------------------------------------------------- matrix-based ---
 class CsrMatrix:
     """The operator assembled as a CSR matrix (mfsem_csr_*): the matrix-based
-    path the paper compares the matrix-free one with."""
+    path the paper compares the matrix-free one with.  pattern "element" stores
+    every pair of nodes that share an element (collocation's zeros included, as
+    a standard assembly does), "coupled" only the pairs that share a lattice
+    coordinate (the entries collocation can make non-zero)."""
 
-    def __init__(self, op: Operator):
+    PATTERNS = {"element": 0, "coupled": 1}
+
+    def __init__(self, op: Operator, pattern: str = "element"):
+        if pattern not in self.PATTERNS:
+            raise ValueError(f"pattern must be one of {sorted(self.PATTERNS)}")
         lib = L.load()
+        code = self.PATTERNS[pattern]
         nnz = C.c_int64()
-        L.check(lib.mfsem_csr_nnz(op.handle, C.byref(nnz)))
+        L.check(lib.mfsem_csr_nnz(op.handle, code, C.byref(nnz)))
+        self.pattern = pattern
         self.n, self.nnz, self.device = op.n_dof, nnz.value, op.device
         self.row_ptr = torch.empty(self.n + 1, dtype=torch.int64, device=op.device)
         self.col = torch.empty(self.nnz, dtype=torch.int32, device=op.device)
         self.val = torch.empty(self.nnz, dtype=torch.float64, device=op.device)
-        L.check(lib.mfsem_csr_assemble(op.handle, _ptr(self.row_ptr), _ptr(self.col),
+        L.check(lib.mfsem_csr_assemble(op.handle, code, _ptr(self.row_ptr), _ptr(self.col),
                                        _ptr(self.val), _stream()))
 
     def apply(self, x, out=None):

@@ -409,22 +409,28 @@ void check_csr_op(const mfsem_op* op) {
     fail(MFSEM_EUNSUPPORTED,
          "the assembled matrix needs a structured GLL lattice, batch 1 and FP64 geometry");
 }
+void check_csr_pattern(int pattern) {
+  require(pattern == MFSEM_CSR_ELEMENT || pattern == MFSEM_CSR_COUPLED,
+          "pattern must be MFSEM_CSR_ELEMENT or MFSEM_CSR_COUPLED");
+}
 }  // namespace
 
-mfsem_status mfsem_csr_nnz(const mfsem_op* op, int64_t* nnz) {
+mfsem_status mfsem_csr_nnz(const mfsem_op* op, int pattern, int64_t* nnz) {
   return guarded([&] {
     check_csr_op(op);
+    check_csr_pattern(pattern);
     require(nnz != nullptr, "NULL argument");
-    *nnz = csr_nnz(*op);
+    *nnz = csr_nnz(*op, pattern == MFSEM_CSR_COUPLED);
   });
 }
 
-mfsem_status mfsem_csr_assemble(const mfsem_op* op, int64_t* row_ptr, int32_t* col, double* val,
-                                void* stream) {
+mfsem_status mfsem_csr_assemble(const mfsem_op* op, int pattern, int64_t* row_ptr, int32_t* col,
+                                double* val, void* stream) {
   return guarded([&] {
     check_csr_op(op);
+    check_csr_pattern(pattern);
     require(row_ptr && col && val, "NULL argument");
-    csr_assemble(*op, row_ptr, col, val, as_stream(stream));
+    csr_assemble(*op, pattern == MFSEM_CSR_COUPLED, row_ptr, col, val, as_stream(stream));
   });
 }
 

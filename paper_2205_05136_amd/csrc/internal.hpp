@@ -159,8 +159,9 @@ void launch_lattice_check(const mfsem_op& op, unsigned long long* bad, hipStream
 void launch_grad_sigma(const mfsem_op& op, const double* u, const double* w, double scale,
                        double* g, hipStream_t s);
 // matrix-based path on structured lattices (csr.hip)
-int64_t csr_nnz(const mfsem_op& op);
-void csr_assemble(const mfsem_op& op, int64_t* row_ptr, int32_t* col, double* val, hipStream_t s);
+int64_t csr_nnz(const mfsem_op& op, bool coupled);
+void csr_assemble(const mfsem_op& op, bool coupled, int64_t* row_ptr, int32_t* col, double* val,
+                  hipStream_t s);
 void csr_spmv(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col, const double* val,
               const double* x, double* y, hipStream_t s);
 

@@ -119,7 +119,7 @@ def test_null_handles_are_rejected_without_a_device():
     n = (C.c_int32 * 3)(3, 2, 2)
     assert lib.mfsem_box_parents(n, None, None, None) == -1
     nnz = C.c_int64()
-    assert lib.mfsem_csr_nnz(None, C.byref(nnz)) == -1
+    assert lib.mfsem_csr_nnz(None, 0, C.byref(nnz)) == -1
     assert lib.mfsem_csr_spmv(-1, 0, None, None, None, None, None, None) == -1
     assert lib.mfsem_extrapolate(-1, None, None, None, None) == -1
     assert lib.mfsem_extrapolate(5, None, None, None, None) == -1

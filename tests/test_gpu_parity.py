@@ -201,30 +201,67 @@ def test_empty_mesh(quad, q, n_dof):
         assert info.status == [-6], info
 
 
+def _row_lengths(spec, pattern):
+    """Row lengths of the CSR patterns on a lattice: along each axis a node's
+    elements span p + 1 nodes (2p + 1 on an interior element face); the element
+    pattern holds the product of the three spans, the coupled one leaves out the
+    nodes differing from the row's node in all three coordinates."""
+    p = spec.p
+    counts = [np.array([p + 1 if i % p else (2 * p + 1 if 0 < i < p * n else p + 1)
+                        for i in range(p * n + 1)]) for n in spec.n]
+    full = np.einsum("k,j,i->kji", counts[2], counts[1], counts[0]).reshape(-1)
+    if pattern == "element":
+        return full
+    return full - np.einsum("k,j,i->kji", counts[2] - 1, counts[1] - 1, counts[0] - 1).reshape(-1)
+
+
+@pytest.mark.parametrize("pattern", ["element", "coupled"])
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 6, 8])
-def test_assembled_matrix(p):
+def test_assembled_matrix(p, pattern):
     """The matrix-based path: the CSR matrix assembled on the GPU equals the
     oracle's assembly of the element matrices, and its product the matrix-free
-    apply."""
+    apply.  The element pattern holds every node pair sharing an element; the
+    coupled one only those that also share a lattice coordinate (under GLL
+    collocation the others are zero, so the oracle's matrix must still be
+    matched entry for entry)."""
     import scipy.sparse as sp
-    announce(f"csr p{p}")
+    announce(f"csr p{p} {pattern}")
     spec = _spec(p, (3, 2, 2) if p <= 5 else (2, 2, 1))
     prob, A, M, K = oracle_problem(spec, sigma_seed=5)
     op, _ = _op(spec, sigma=to_dev(prob.sigma))
-    csr = mf.CsrMatrix(op)
+    csr = mf.CsrMatrix(op, pattern)
     rp, col, val = csr.row_ptr.cpu().numpy(), csr.col.cpu().numpy().astype(np.int64), to_np(csr.val)
     assert rp[0] == 0 and rp[-1] == csr.nnz == len(col)
-    # row extents along each axis of the element-connectivity pattern
-    P = p + 1
-    counts = [np.array([P if i % p else (2 * p + 1 if 0 < i < p * n else p + 1)
-                        for i in range(p * n + 1)]) for n in spec.n]
-    expect = np.einsum("k,j,i->kji", counts[2], counts[1], counts[0]).reshape(-1)
-    assert np.array_equal(np.diff(rp), expect)
+    assert np.array_equal(np.diff(rp), _row_lengths(spec, pattern))
     assert all(np.all(np.diff(col[rp[r]:rp[r + 1]]) > 0) for r in range(0, spec.n_dof, 7))
+    if pattern == "coupled":
+        NX, NY = p * spec.n[0] + 1, p * spec.n[1] + 1
+        ijk = lambda g: (g % NX, (g // NX) % NY, g // (NX * NY))
+        for r in range(0, spec.n_dof, 5):
+            c = ijk(col[rp[r]:rp[r + 1]])
+            share = (c[0] == ijk(r)[0]) | (c[1] == ijk(r)[1]) | (c[2] == ijk(r)[2])
+            assert bool(share.all()), r
     Ag = sp.csr_matrix((val, col, rp), shape=A.shape)
     assert abs(Ag - A).max() <= 1e-13 * abs(A).max()
     x = synth.uniform(104, spec.n_dof)
     assert rel_l2(to_np(csr.apply(to_dev(x))), A @ x) <= TOL64
+
+
+def test_assembled_matrix_patterns_agree_at_full_size():
+    """On the 229,425-DOF c2 slab at p = 4 (the matrix-based comparison's mesh):
+    both patterns have their closed-form sizes, the coupled one holds every
+    non-zero of the element pattern, and the two products agree."""
+    announce("csr patterns c2")
+    spec = synth.C2
+    op, _ = _op(spec)
+    full, cpl = mf.CsrMatrix(op, "element"), mf.CsrMatrix(op, "coupled")
+    assert full.nnz == int(_row_lengths(spec, "element").sum())
+    assert cpl.nnz == int(_row_lengths(spec, "coupled").sum())
+    assert int(torch.count_nonzero(full.val)) == int(torch.count_nonzero(cpl.val))
+    x = to_dev(synth.uniform(105, spec.n_dof))
+    y1, y2 = full.apply(x), cpl.apply(x)
+    assert float(torch.linalg.norm(y1 - y2)) <= 1e-14 * float(torch.linalg.norm(y1))
+    assert rel_l2(to_np(y1), to_np(op.apply(x))) <= TOL64
 
 
 @pytest.mark.parametrize("p,quad,q", [(2, "gll", 0), (4, "gll", 0), (5, "gll", 0), (6, "gll", 0),
