@@ -216,7 +216,7 @@ def _row_lengths(spec, pattern):
 
 
 @pytest.mark.parametrize("pattern", ["element", "coupled"])
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 6, 8])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_assembled_matrix(p, pattern):
     """The matrix-based path: the CSR matrix assembled on the GPU equals the
     oracle's assembly of the element matrices, and its product the matrix-free
@@ -245,6 +245,20 @@ def test_assembled_matrix(p, pattern):
     assert abs(Ag - A).max() <= 1e-13 * abs(A).max()
     x = synth.uniform(104, spec.n_dof)
     assert rel_l2(to_np(csr.apply(to_dev(x))), A @ x) <= TOL64
+
+
+def test_assembled_matrix_rejects_unknown_patterns():
+    """An unknown pattern code is EINVAL from the library (and a ValueError from
+    the binding), with nothing written."""
+    import ctypes as C
+    from paper_2205_05136_amd import _lib as L
+    announce("csr unknown pattern")
+    op, _ = _op(_spec(2, (2, 2, 1)))
+    nnz = C.c_int64(-5)
+    assert L.load().mfsem_csr_nnz(op.handle, 2, C.byref(nnz)) == -1 and nnz.value == -5
+    assert L.load().mfsem_csr_nnz(op.handle, -1, C.byref(nnz)) == -1 and nnz.value == -5
+    with pytest.raises(ValueError):
+        mf.CsrMatrix(op, "full")
 
 
 def test_assembled_matrix_patterns_agree_at_full_size():
