@@ -470,6 +470,26 @@ def _csr_point(mf, op, x, t_mf_ms, spec, pattern, max_bytes):
            "spmv_ms": round(t_spmv, 4), "spmv_gdofs": round(spec.n_dof / (t_spmv * 1e-3) / 1e9, 3),
            "spmv_hbm_frac": round(moved / (t_spmv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "matrix_free_speedup": round(t_spmv / t_mf_ms, 2)}
+    # the same matrix through the vendor sparse library (torch's CSR product on
+    # the GPU, int32 indices), for comparison with the hand-written SpMV
+    try:
+        At = torch.sparse_csr_tensor(A.row_ptr.to(torch.int32), A.col, A.val,
+                                     size=(spec.n_dof, spec.n_dof))
+        yl = At @ x
+        err = float(torch.linalg.norm(yl - y) / torch.linalg.norm(y))
+        for _ in range(3):
+            At @ x
+        a.record()
+        for _ in range(R):
+            At @ x
+        b.record()
+        torch.cuda.synchronize()
+        out["library_spmv_ms"] = round(a.elapsed_time(b) / R, 4)
+        out["library_vs_own_rel_l2"] = err
+        del At, yl
+    except (RuntimeError, NotImplementedError) as exc:
+        out["library_spmv_ms"] = None
+        out["library_note"] = str(exc)[:200]
     del A
     torch.cuda.empty_cache()
     return out
